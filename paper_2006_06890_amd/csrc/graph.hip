@@ -1,0 +1,391 @@
+// Graph handle: validation and placement of the CSR (EMOGI Sec. 4.2: the
+// vertex list and per-vertex buffers go to GPU memory, the edge list to host
+// memory, all mapped once at set-up; Sec. 3.1: pinned + mapped host memory is
+// what lets GPU threads read it in place).
+#include "internal.h"
+
+#include <cstdarg>
+#include <cstdlib>
+#include <cstring>
+#include <thread>
+#include <vector>
+#include <algorithm>
+#include <atomic>
+#include <new>
+
+namespace emogi {
+
+static thread_local char g_last_error[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+// Runs fn(begin, end) over [0, n) on up to hardware_concurrency threads.
+template <class F>
+static void parallel_for(uint64_t n, F fn) {
+    unsigned t = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < (1u << 16) || t == 1) {
+        fn(uint64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    uint64_t step = (n + t - 1) / t;
+    for (unsigned i = 0; i < t; ++i) {
+        uint64_t b = i * step, e = std::min(n, b + step);
+        if (b >= e) break;
+        th.emplace_back([=] { fn(b, e); });
+    }
+    for (auto &x : th) x.join();
+}
+
+static void parallel_copy(void *dst, const void *src, size_t bytes) {
+    const size_t grain = size_t(1) << 22;
+    uint64_t blocks = (bytes + grain - 1) / grain;
+    parallel_for(blocks, [&](uint64_t b, uint64_t e) {
+        for (uint64_t i = b; i < e; ++i) {
+            size_t off = i * grain, len = std::min(grain, bytes - off);
+            memcpy(static_cast<char *>(dst) + off, static_cast<const char *>(src) + off, len);
+        }
+    });
+}
+
+static inline uint64_t col_at(const void *col, uint32_t cb, uint64_t i) {
+    return cb == 4 ? static_cast<const uint32_t *>(col)[i] : static_cast<const uint64_t *>(col)[i];
+}
+
+// 0 when well formed, else an EMOGI_E_* code with the reason recorded.
+static emogi_status_t validate(const uint64_t *rp, uint64_t V, const void *col, uint32_t cb,
+                               bool symmetric) {
+    if (rp[0] != 0) {
+        set_error("row_ptr[0] must be 0");
+        return EMOGI_E_INVALID;
+    }
+    for (uint64_t u = 0; u < V; ++u)
+        if (rp[u + 1] < rp[u]) {
+            set_error("row_ptr decreases at vertex %llu", (unsigned long long)u);
+            return EMOGI_E_INVALID;
+        }
+    std::atomic<int> bad{0};
+    parallel_for(V, [&](uint64_t b, uint64_t e) {
+        for (uint64_t u = b; u < e && !bad.load(std::memory_order_relaxed); ++u)
+            for (uint64_t i = rp[u]; i < rp[u + 1]; ++i)
+                if (col_at(col, cb, i) >= V) {
+                    bad = 1;
+                    break;
+                }
+    });
+    if (bad) {
+        set_error("a neighbour id is >= num_vertices");
+        return EMOGI_E_INVALID;
+    }
+    if (!symmetric) return EMOGI_OK;
+    // u->v must have v->u: sort a copy of each list, then binary-search.
+    uint64_t E = rp[V];
+    std::vector<uint64_t> sorted(E);
+    parallel_for(V, [&](uint64_t b, uint64_t e) {
+        for (uint64_t u = b; u < e; ++u) {
+            for (uint64_t i = rp[u]; i < rp[u + 1]; ++i) sorted[i] = col_at(col, cb, i);
+            std::sort(sorted.begin() + rp[u], sorted.begin() + rp[u + 1]);
+        }
+    });
+    parallel_for(V, [&](uint64_t b, uint64_t e) {
+        for (uint64_t u = b; u < e && !bad.load(std::memory_order_relaxed); ++u)
+            for (uint64_t i = rp[u]; i < rp[u + 1]; ++i) {
+                uint64_t v = sorted[i];
+                if (!std::binary_search(sorted.begin() + rp[v], sorted.begin() + rp[v + 1], u)) {
+                    bad = 1;
+                    break;
+                }
+            }
+    });
+    if (bad) {
+        set_error("graph is not symmetric");
+        return EMOGI_E_NOT_SYMMETRIC;
+    }
+    return EMOGI_OK;
+}
+
+static void release(emogi_graph_s *g) {
+    if (!g) return;
+    auto free_edges = [](void *p, emogi_graph_s::Kind k) {
+        if (!p) return;
+        if (k == emogi_graph_s::DEVICE || k == emogi_graph_s::MANAGED) (void)hipFree(p);
+        if (k == emogi_graph_s::PINNED) (void)hipHostFree(p);
+    };
+    free_edges(g->col, g->col_kind);
+    free_edges(g->weights, g->w_kind);
+    if (g->row_ptr) (void)hipFree(g->row_ptr);
+    Pool &p = g->pool;
+    for (auto q : p.queue)
+        if (q) (void)hipFree(q);
+    if (p.bitmap) (void)hipFree(p.bitmap);
+    if (p.stamp) (void)hipFree(p.stamp);
+    if (p.chunk_scan) (void)hipFree(p.chunk_scan);
+    if (p.block_sums) (void)hipFree(p.block_sums);
+    if (p.counters) (void)hipFree(p.counters);
+    if (p.host_counters) (void)hipHostFree(p.host_counters);
+    if (p.features) (void)hipFree(p.features);
+    if (p.degree_hist) (void)hipFree(p.degree_hist);
+    if (g->mlp_params) (void)hipFree(g->mlp_params);
+    for (hipEvent_t e : {g->ev_begin, g->ev_end, g->ev_k0, g->ev_k1})
+        if (e) (void)hipEventDestroy(e);
+    delete g;
+}
+
+// Places one edge-sized array (col or weights) per the placement.
+static emogi_status_t place(emogi_graph_s *g, const void *src, size_t bytes, void **dst,
+                            emogi_graph_s::Kind *kind) {
+    if (bytes == 0) bytes = 8;  // keep a valid pointer for empty graphs
+    switch (g->placement) {
+    case EMOGI_PLACE_HBM: {
+        void *d = nullptr;
+        if (hipMalloc(&d, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of %zu bytes for the edge list failed", bytes);
+            return EMOGI_E_OOM_DEVICE;
+        }
+        *dst = d;
+        *kind = emogi_graph_s::DEVICE;
+        if (src) EMOGI_HIP_TRY(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice), EMOGI_E_HIP);
+        return EMOGI_OK;
+    }
+    case EMOGI_PLACE_HOST_ZERO_COPY: {
+        if (g->flags & EMOGI_F_BORROW) {
+            hipPointerAttribute_t attr;
+            if (!src || hipPointerGetAttributes(&attr, src) != hipSuccess ||
+                attr.type != hipMemoryTypeHost) {
+                (void)hipGetLastError();
+                set_error("EMOGI_F_BORROW needs memory from emogi_host_alloc");
+                return EMOGI_E_INVALID;
+            }
+            void *d = nullptr;
+            EMOGI_HIP_TRY(hipHostGetDevicePointer(&d, const_cast<void *>(src), 0), EMOGI_E_HIP);
+            *dst = d;
+            *kind = emogi_graph_s::BORROWED;
+            return EMOGI_OK;
+        }
+        unsigned fl = hipHostMallocMapped;
+        if (g->flags & EMOGI_F_PIN_NONCOHERENT) fl |= hipHostMallocNonCoherent;
+        void *h = nullptr;
+        if (hipHostMalloc(&h, bytes, fl) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipHostMalloc of %zu pinned bytes failed", bytes);
+            return EMOGI_E_OOM_HOST;
+        }
+        *kind = emogi_graph_s::PINNED;
+        void *d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipHostFree(h);
+            *kind = emogi_graph_s::NONE;
+            set_error("hipHostGetDevicePointer failed");
+            return EMOGI_E_HIP;
+        }
+        *dst = d;
+        if (src) parallel_copy(h, src, bytes);
+        return EMOGI_OK;
+    }
+    case EMOGI_PLACE_MANAGED: {
+        int dev = g->device, managed = 0;
+        (void)hipDeviceGetAttribute(&managed, hipDeviceAttributeManagedMemory, dev);
+        if (!managed) {
+            set_error("managed memory is not supported on this device (no XNACK/HMM)");
+            return EMOGI_E_UNSUPPORTED;
+        }
+        void *m = nullptr;
+        if (hipMallocManaged(&m, bytes, hipMemAttachGlobal) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMallocManaged of %zu bytes failed", bytes);
+            return EMOGI_E_OOM_HOST;
+        }
+        *dst = m;
+        *kind = emogi_graph_s::MANAGED;
+        if (src) parallel_copy(m, src, bytes);
+        // Sec. 5.1 (a): the UVM baseline marks the edge list read-mostly.
+        (void)hipMemAdvise(m, bytes, hipMemAdviseSetReadMostly, dev);
+        (void)hipGetLastError();
+        return EMOGI_OK;
+    }
+    }
+    set_error("unknown placement %d", (int)g->placement);
+    return EMOGI_E_INVALID;
+}
+
+}  // namespace emogi
+
+using namespace emogi;
+
+extern "C" {
+
+emogi_status_t emogi_host_alloc(size_t bytes, uint32_t flags, void **out) {
+    if (!out || bytes == 0) {
+        set_error("emogi_host_alloc: null out or zero size");
+        return EMOGI_E_INVALID;
+    }
+    unsigned fl = hipHostMallocMapped;
+    if (flags & EMOGI_F_PIN_NONCOHERENT) fl |= hipHostMallocNonCoherent;
+    void *h = nullptr;
+    if (hipHostMalloc(&h, bytes, fl) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipHostMalloc of %zu bytes failed", bytes);
+        return EMOGI_E_OOM_HOST;
+    }
+    *out = h;
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_host_free(void *p) {
+    if (!p) return EMOGI_OK;
+    EMOGI_HIP_TRY(hipHostFree(p), EMOGI_E_HIP);
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const void *col,
+                                  uint32_t col_bytes, const uint32_t *weights,
+                                  emogi_placement_t placement, uint32_t flags,
+                                  emogi_graph_t *out) {
+    if (!out || !row_ptr) {
+        set_error("emogi_graph_create: null row_ptr or out");
+        return EMOGI_E_INVALID;
+    }
+    if (col_bytes != 4 && col_bytes != 8) {
+        set_error("col_bytes must be 4 or 8");
+        return EMOGI_E_INVALID;
+    }
+    if (V >= 0xFFFFFFFFull) {
+        set_error("num_vertices must be below 2^32-1 (outputs are uint32)");
+        return EMOGI_E_UNSUPPORTED;
+    }
+    if ((int)placement < 0 || (int)placement > 2) {
+        set_error("unknown placement %d", (int)placement);
+        return EMOGI_E_INVALID;
+    }
+    uint64_t E = row_ptr[V];
+    if (E > 0 && !col) {
+        set_error("col is null but the graph has edges");
+        return EMOGI_E_INVALID;
+    }
+    if ((flags & EMOGI_F_BORROW) && placement != EMOGI_PLACE_HOST_ZERO_COPY) {
+        set_error("EMOGI_F_BORROW is only valid with host zero-copy placement");
+        return EMOGI_E_INVALID;
+    }
+    if (flags & EMOGI_F_VALIDATE) {
+        emogi_status_t st = validate(row_ptr, V, col, col_bytes, (flags & EMOGI_F_SYMMETRIC) != 0);
+        if (st != EMOGI_OK) return st;
+    }
+    int dev = 0;
+    EMOGI_HIP_TRY(hipGetDevice(&dev), EMOGI_E_HIP);
+
+    auto *g = new (std::nothrow) emogi_graph_s();
+    if (!g) {
+        set_error("out of host memory");
+        return EMOGI_E_OOM_HOST;
+    }
+    g->V = V;
+    g->E = E;
+    g->col_bytes = col_bytes;
+    g->flags = flags;
+    g->placement = placement;
+    g->device = dev;
+    uint64_t maxd = 0;
+    for (uint64_t u = 0; u < V; ++u) maxd = std::max(maxd, row_ptr[u + 1] - row_ptr[u]);
+    g->max_degree = maxd;
+
+    emogi_status_t st = EMOGI_OK;
+    if (hipMalloc(&g->row_ptr, (V + 1) * sizeof(uint64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        g->row_ptr = nullptr;
+        release(g);
+        set_error("hipMalloc of row_ptr failed");
+        return EMOGI_E_OOM_DEVICE;
+    }
+    if (hipMemcpy(g->row_ptr, row_ptr, (V + 1) * sizeof(uint64_t), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        release(g);
+        set_error("copy of row_ptr failed");
+        return EMOGI_E_HIP;
+    }
+    st = place(g, col, E * col_bytes, &g->col, &g->col_kind);
+    if (st == EMOGI_OK && weights) {
+        void *w = nullptr;
+        st = place(g, weights, E * sizeof(uint32_t), &w, &g->w_kind);
+        g->weights = static_cast<uint32_t *>(w);
+    }
+    if (st == EMOGI_OK) {
+        for (hipEvent_t *e : {&g->ev_begin, &g->ev_end, &g->ev_k0, &g->ev_k1})
+            if (hipEventCreate(e) != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("hipEventCreate failed");
+                st = EMOGI_E_HIP;
+                break;
+            }
+    }
+    if (st != EMOGI_OK) {
+        release(g);
+        return st;
+    }
+    *out = g;
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_graph_destroy(emogi_graph_t g) {
+    if (!g) return EMOGI_E_INVALID;
+    (void)hipDeviceSynchronize();
+    release(g);
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_set_request_unit(emogi_graph_t g, uint32_t bytes) {
+    if (!g || bytes < 32 || bytes > 4096 || (bytes & (bytes - 1))) {
+        set_error("request unit must be a power of two in [32, 4096]");
+        return EMOGI_E_INVALID;
+    }
+    g->request_unit = bytes;
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_set_scheduler(emogi_graph_t g, int mode) {
+    if (!g || !((mode >= 0 && mode < EMOGI_NUM_VARIANTS) || mode == EMOGI_SCHED_HEURISTIC ||
+                mode == EMOGI_SCHED_LEARNED)) {
+        set_error("unknown scheduler mode %d", mode);
+        return EMOGI_E_INVALID;
+    }
+    g->sched_mode = mode;
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_last_stats(emogi_graph_t g, emogi_stats_t *out) {
+    if (!g || !out) {
+        set_error("null argument");
+        return EMOGI_E_INVALID;
+    }
+    *out = g->stats;
+    return EMOGI_OK;
+}
+
+uint64_t emogi_num_vertices(emogi_graph_t g) { return g ? g->V : 0; }
+uint64_t emogi_num_edges(emogi_graph_t g) { return g ? g->E : 0; }
+
+const char *emogi_strerror(emogi_status_t e) {
+    switch (e) {
+    case EMOGI_OK: return "ok";
+    case EMOGI_E_INVALID: return "invalid argument";
+    case EMOGI_E_OOM_HOST: return "out of host memory";
+    case EMOGI_E_OOM_DEVICE: return "out of device memory";
+    case EMOGI_E_HIP: return "HIP runtime error";
+    case EMOGI_E_NOT_SYMMETRIC: return "graph is not symmetric";
+    case EMOGI_E_OVERFLOW: return "distance overflow";
+    case EMOGI_E_NOCONVERGE: return "iteration cap reached";
+    case EMOGI_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *emogi_last_error(void) { return g_last_error; }
+
+}  // extern "C"

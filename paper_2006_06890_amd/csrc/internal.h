@@ -1,0 +1,74 @@
+// Internal definitions of the zero-copy traversal library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/emogi.h"
+
+namespace emogi {
+
+// Thread-local message of the last failing call.
+void set_error(const char *fmt, ...);
+
+#define EMOGI_HIP_TRY(expr, code)                                                  \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            (void)hipGetLastError();                                               \
+            ::emogi::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                               __FILE__, __LINE__);                               \
+            return (code);                                                         \
+        }                                                                          \
+    } while (0)
+
+// Device counters written by the scan kernels; copied to host once per level.
+enum Counter : int {
+    C_NEXT = 0,      // entries pushed to the next frontier
+    C_EDGES = 1,     // sum of degrees of expanded vertices
+    C_REQBYTES = 2,  // request-granular link bytes of those lists
+    C_OVERFLOW = 3,  // SSSP: some relaxation exceeded 0xFFFFFFFE
+    C_VERTS = 4,     // expanded vertices
+    C_COUNT = 8
+};
+
+struct Pool {
+    uint32_t *queue[2] = {nullptr, nullptr}; // frontier ids, V entries each
+    uint32_t *bitmap = nullptr;               // BFS visited / SSSP overflow marks
+    uint32_t *stamp = nullptr;                // SSSP/CC: round in which v was last pushed
+    uint64_t *chunk_scan = nullptr;           // V5: exclusive scan of per-entry chunk counts
+    uint64_t *block_sums = nullptr;           // V5: scan partials
+    unsigned long long *counters = nullptr;   // C_COUNT device counters
+    unsigned long long *host_counters = nullptr; // pinned mirror
+    float *features = nullptr;                // scheduler features (device)
+    uint32_t *degree_hist = nullptr;          // scheduler degree histogram (device)
+    size_t chunk_cap = 0;
+};
+
+}  // namespace emogi
+
+struct emogi_graph_s {
+    uint64_t V = 0, E = 0;
+    uint32_t col_bytes = 4;
+    uint32_t flags = 0;
+    emogi_placement_t placement = EMOGI_PLACE_HOST_ZERO_COPY;
+    int device = 0;
+
+    uint64_t *row_ptr = nullptr;   // device (HBM)
+    void *col = nullptr;           // device-dereferenceable edge list
+    uint32_t *weights = nullptr;   // device-dereferenceable weights or null
+    // ownership of the edge storage
+    enum Kind { NONE, DEVICE, PINNED, MANAGED, BORROWED } col_kind = NONE, w_kind = NONE;
+
+    uint32_t request_unit = 256;
+    int sched_mode = EMOGI_SCHED_HEURISTIC;
+    float *mlp_params = nullptr;   // device, 5638 floats, or null
+    uint64_t max_degree = 0;
+
+    emogi::Pool pool;
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;
+    emogi_stats_t stats{};
+};

@@ -1,0 +1,200 @@
+// Per-level choice of the access variant.
+//
+// EMOGI fixes the worker at one warp per vertex and notes (Sec. 4.3.1) that a
+// finer worker only pays when the graph is in GPU memory with low degrees;
+// Sec. 5.3.1 shows alignment pays least on uniformly low-degree graphs.  So no
+// variant wins on every frontier.  The scheduler reads 16 features of the
+// current frontier and picks one of the six result-identical variants, either
+// by a fixed rule or by a 16-64-64-6 MLP whose inference runs in one wave here.
+// The features are computed on the GPU from the frontier queue and row_ptr.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace emogi {
+
+int heuristic_variant(const emogi_graph_s *g, uint64_t n);
+
+constexpr int kNIn = 16, kNH = 64, kNOut = 6;
+constexpr int kNParams = kNH * kNIn + kNH + kNH * kNH + kNH + kNOut * kNH + kNOut;  // 5638
+constexpr int kHistBins = 8;
+
+// acc[0..7]: degree histogram of the frontier, acc[8]: sum of degrees.
+__global__ __launch_bounds__(256) void k_frontier_hist(const uint32_t *queue, uint32_t n,
+                                                       const uint64_t *row_ptr,
+                                                       unsigned long long *acc) {
+    __shared__ unsigned long long s_acc[kHistBins + 1];
+    if (threadIdx.x < kHistBins + 1) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long local[kHistBins + 1] = {};
+    for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n;
+         q += uint64_t(gridDim.x) * blockDim.x) {
+        const uint32_t u = queue ? queue[q] : uint32_t(q);
+        const uint64_t d = row_ptr[u + 1] - row_ptr[u];
+        // bins: <=1, [2,4), [4,8), [8,16), [16,64), [64,256), [256,4096), >=4096
+        int bin = d <= 1 ? 0 : d < 4 ? 1 : d < 8 ? 2 : d < 16 ? 3 : d < 64 ? 4 : d < 256 ? 5 : d < 4096 ? 6 : 7;
+        local[bin] += 1;
+        local[kHistBins] += d;
+    }
+    for (int i = 0; i < kHistBins + 1; ++i)
+        if (local[i]) atomicAdd(&s_acc[i], local[i]);
+    __syncthreads();
+    if (threadIdx.x < kHistBins + 1 && s_acc[threadIdx.x]) atomicAdd(&acc[threadIdx.x], s_acc[threadIdx.x]);
+}
+
+struct FeatureConsts {
+    float n, V, E, col8, weights, zero_copy, managed;
+};
+
+// One wave: features from the histogram, then z = W3 relu(W2 relu(W1 x + b1) + b2) + b3,
+// argmax into *choice.  Also stores the features for harvesting.
+__global__ __launch_bounds__(64) void k_mlp_pick(const unsigned long long *acc, FeatureConsts c,
+                                                 const float *params, int *choice, float *feat_out) {
+    __shared__ float x[kNIn], h1[kNH], h2[kNH], z[kNOut];
+    const int t = threadIdx.x;
+    if (t == 0) {
+        const float sumdeg = float(acc[kHistBins]);
+        x[0] = log2f(1.f + c.n) / 32.f;
+        x[1] = c.n / fmaxf(c.V, 1.f);
+        x[2] = log2f(1.f + sumdeg) / 40.f;
+        x[3] = sumdeg / fmaxf(c.E, 1.f);
+        for (int b = 0; b < kHistBins; ++b) x[4 + b] = float(acc[b]) / fmaxf(c.n, 1.f);
+        x[12] = c.col8;
+        x[13] = c.weights;
+        x[14] = c.zero_copy;
+        x[15] = c.managed;
+    }
+    __syncthreads();
+    if (t < kNIn && feat_out) feat_out[t] = x[t];
+    const float *W1 = params, *b1 = W1 + kNH * kNIn, *W2 = b1 + kNH, *b2 = W2 + kNH * kNH,
+                *W3 = b2 + kNH, *b3 = W3 + kNOut * kNH;
+    if (params) {
+        float a = b1[t];
+        for (int k = 0; k < kNIn; ++k) a += W1[t * kNIn + k] * x[k];
+        h1[t] = fmaxf(a, 0.f);
+        __syncthreads();
+        a = b2[t];
+        for (int k = 0; k < kNH; ++k) a += W2[t * kNH + k] * h1[k];
+        h2[t] = fmaxf(a, 0.f);
+        __syncthreads();
+        if (t < kNOut) {
+            a = b3[t];
+            for (int k = 0; k < kNH; ++k) a += W3[t * kNH + k] * h2[k];
+            z[t] = a;
+        }
+        __syncthreads();
+        if (t == 0) {
+            int best = 0;
+            for (int j = 1; j < kNOut; ++j)
+                if (z[j] > z[best]) best = j;
+            *choice = best;
+        }
+    }
+}
+
+// Scratch for the scheduler: acc (9 u64), choice (int) and features (16 f32).
+struct SchedScratch {
+    unsigned long long *acc;
+    int *choice;
+    float *feat;
+};
+
+static emogi_status_t sched_scratch(emogi_graph_s *g, SchedScratch *s) {
+    Pool &p = g->pool;
+    if (!p.degree_hist) {
+        // layout: [acc: 9 x u64][choice: int][pad][features: 16 f32]
+        if (hipMalloc(&p.degree_hist, 256) != hipSuccess) {
+            (void)hipGetLastError();
+            p.degree_hist = nullptr;
+            set_error("scheduler scratch allocation failed");
+            return EMOGI_E_OOM_DEVICE;
+        }
+    }
+    char *base = reinterpret_cast<char *>(p.degree_hist);
+    s->acc = reinterpret_cast<unsigned long long *>(base);
+    s->choice = reinterpret_cast<int *>(base + 96);
+    s->feat = reinterpret_cast<float *>(base + 128);
+    return EMOGI_OK;
+}
+
+// Frontier features (and the MLP's pick when weights are loaded).
+// Returns the variant, or -1 on a HIP failure.
+static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue,
+                        hipStream_t stream, float *features_host) {
+    SchedScratch s;
+    if (sched_scratch(g, &s) != EMOGI_OK) return -1;
+    if (hipMemsetAsync(s.acc, 0, 128, stream) != hipSuccess) return -1;
+    const unsigned grid = unsigned(std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 1024)));
+    hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, uint32_t(n),
+                       g->row_ptr, s.acc);
+    FeatureConsts c;
+    c.n = float(n);
+    c.V = float(g->V);
+    c.E = float(g->E);
+    c.col8 = g->col_bytes == 8 ? 1.f : 0.f;
+    c.weights = algo == 1 ? 1.f : 0.f;
+    c.zero_copy = g->placement == EMOGI_PLACE_HOST_ZERO_COPY ? 1.f : 0.f;
+    c.managed = g->placement == EMOGI_PLACE_MANAGED ? 1.f : 0.f;
+    hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(64), 0, stream, s.acc, c, g->mlp_params, s.choice,
+                       s.feat);
+    struct {
+        int choice;
+        float feat[kNIn];
+    } h;
+    if (hipMemcpyAsync(&h.choice, s.choice, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(h.feat, s.feat, sizeof(h.feat), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    if (features_host) memcpy(features_host, h.feat, sizeof(h.feat));
+    if (!g->mlp_params || h.choice < 0 || h.choice >= kNOut) return heuristic_variant(g, n);
+    return h.choice;
+}
+
+int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue, hipStream_t stream) {
+    const int m = g->sched_mode;
+    if (m >= 0 && m < EMOGI_NUM_VARIANTS) return m;
+    if (m == EMOGI_SCHED_LEARNED && g->mlp_params) {
+        int v = learned_pick(g, algo, n, queue, stream, nullptr);
+        if (v >= 0) return v;
+    }
+    return heuristic_variant(g, n);
+}
+
+}  // namespace emogi
+
+using namespace emogi;
+
+extern "C" {
+
+emogi_status_t emogi_set_scheduler_weights(emogi_graph_t g, const float *params, size_t count) {
+    if (!g) {
+        set_error("null graph");
+        return EMOGI_E_INVALID;
+    }
+    if (!params) {
+        if (g->mlp_params) (void)hipFree(g->mlp_params);
+        g->mlp_params = nullptr;
+        return EMOGI_OK;
+    }
+    if (count != size_t(kNParams)) {
+        set_error("expected %d scheduler parameters, got %zu", kNParams, count);
+        return EMOGI_E_INVALID;
+    }
+    if (!g->mlp_params) {
+        if (hipMalloc(&g->mlp_params, kNParams * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            g->mlp_params = nullptr;
+            set_error("hipMalloc for scheduler weights failed");
+            return EMOGI_E_OOM_DEVICE;
+        }
+    }
+    EMOGI_HIP_TRY(hipMemcpy(g->mlp_params, params, kNParams * sizeof(float), hipMemcpyHostToDevice),
+                  EMOGI_E_HIP);
+    return EMOGI_OK;
+}
+
+}  // extern "C"
