@@ -48,6 +48,7 @@ def _load():
             "gg_num_edges": (u64, [p]),
             "gg_export": (i32, [p, p, p, i32, p, u64]),
             "gg_relabel": (i32, [p, p]),
+            "gg_locality_order": (i32, [p, u64, u64, p]),
             "gg_free": (None, [p]),
             "gg_stream_key": (u64, [u64, u64]),
             "gg_draw": (u64, [u64, u64]),
@@ -114,6 +115,14 @@ class Handle:
                          None if w is None else w.ctypes.data, weight_seed)
         return CSR(rp, col, w, symmetric=True, name=self.name)
 
+    def locality_order(self, run=1024, seed=1):
+        """Relabels in first-visit order from the top-degree vertex, runs of ``run`` ids shuffled."""
+        new_id = np.empty(self.num_vertices, dtype=np.uint64)
+        if _load().gg_locality_order(self._p, run, seed, new_id.ctypes.data):
+            raise MemoryError("locality order failed")
+        self.relabel(new_id)
+        return new_id
+
     def relabel(self, new_id):
         new_id = np.ascontiguousarray(new_id, dtype=np.uint64)
         if _load().gg_relabel(self._p, new_id.ctypes.data):
@@ -148,6 +157,16 @@ def chung_lu(num_vertices, samples, gamma=2.1, i0=None, seed=1, permute=True):
         i0 = max(1.0, num_vertices ** 0.1)
     return Handle(_load().gg_chung_lu(num_vertices, samples, gamma, i0, seed, int(permute)),
                   f"chunglu{num_vertices}_g{gamma}_s{seed}")
+
+
+def power_law(num_vertices, mean_degree=36, gamma=2.1, seed=1, run=1024):
+    """Chung-Lu power law with ~mean_degree directed edges per vertex after
+    symmetrising and deduplication, locality-ordered in runs of ``run``."""
+    samples = int(num_vertices * mean_degree / 2 * 1.18)  # ~15% of hub pairs repeat
+    h = chung_lu(num_vertices, samples, gamma=gamma, seed=seed, permute=False)  # relabelled below
+    h.locality_order(run=run, seed=seed)
+    h.name = f"powerlaw{num_vertices}_d{mean_degree}_g{gamma}_s{seed}"
+    return h
 
 
 def stream_key(seed, stream):

@@ -19,7 +19,7 @@
  *   uniform: m samples with both endpoints uniform on [0, 2^scale).
  *   Chung-Lu power law: expected degree of vertex i proportional to
  *     (i + i0)^(-1/(gamma-1)); m samples, each endpoint drawn from that
- *     distribution by inversion of the prefix table.
+ *     distribution with Vose's alias method (one draw per endpoint).
  * Every kind is then symmetrised, self-loops and duplicates dropped, and each
  * neighbour list sorted ascending.
  * Weights: w(u,v) = 1 + (mix64(wkey ^ (min(u,v) << 32 | max(u,v))) mod 255),
@@ -30,6 +30,7 @@
 #include <string.h>
 #include <math.h>
 #include <omp.h>
+#include <stdio.h>
 
 #define GAMMA 0x9E3779B97F4A7C15ull
 
@@ -95,7 +96,8 @@ typedef struct {
     uint32_t ta, tab, tabc; /* R-MAT thresholds on 32-bit uniforms */
     perm_t perm;
     int permute;
-    const double *cdf;      /* Chung-Lu: cumulative weights, length V */
+    const uint32_t *alias_prob; /* Chung-Lu: alias table (Vose 1991), keep-threshold * 2^32 */
+    const uint32_t *alias_idx;  /* Chung-Lu: alias of each slot */
 } sampler_t;
 
 static inline void sample_edge(const sampler_t *s, uint64_t k, uint64_t *pu, uint64_t *pv)
@@ -107,13 +109,10 @@ static inline void sample_edge(const sampler_t *s, uint64_t k, uint64_t *pu, uin
         for (int b = 0; b < levels; ++b) {
             uint64_t x = draw(s->key, base + (uint64_t)(b / 2));
             uint32_t r = (b & 1) ? (uint32_t)x : (uint32_t)(x >> 32);
-            int rb, cb;
-            if (r < s->ta) { rb = 0; cb = 0; }
-            else if (r < s->tab) { rb = 0; cb = 1; }
-            else if (r < s->tabc) { rb = 1; cb = 0; }
-            else { rb = 1; cb = 1; }
-            u = (u << 1) | (uint64_t)rb;
-            v = (v << 1) | (uint64_t)cb;
+            /* quadrant of r: [0,a) -> (0,0), [a,a+b) -> (0,1), [a+b,a+b+c) -> (1,0), else (1,1) */
+            const uint64_t ge_a = r >= s->ta, ge_ab = r >= s->tab, ge_abc = r >= s->tabc;
+            u = (u << 1) | ge_ab;
+            v = (v << 1) | ((ge_a ^ ge_ab) | ge_abc);
         }
         if (s->permute) {
             u = perm_apply(&s->perm, u);
@@ -124,16 +123,12 @@ static inline void sample_edge(const sampler_t *s, uint64_t k, uint64_t *pu, uin
         u = s->scale ? x >> (64 - s->scale) : 0;
         v = s->scale ? y >> (64 - s->scale) : 0;
     } else {
-        /* inversion: first index whose cumulative weight exceeds r */
+        /* alias method: slot from the high half of one draw, keep-or-alias from the low half */
         for (int e = 0; e < 2; ++e) {
-            double r = (double)(draw(s->key, 2 * k + (uint64_t)e) >> 11) * (1.0 / 9007199254740992.0);
-            r *= s->cdf[s->V - 1];
-            uint64_t lo = 0, hi = s->V - 1;
-            while (lo < hi) {
-                uint64_t mid = lo + (hi - lo) / 2;
-                if (s->cdf[mid] > r) hi = mid; else lo = mid + 1;
-            }
-            if (e == 0) u = lo; else v = lo;
+            const uint64_t x = draw(s->key, 2 * k + (uint64_t)e);
+            const uint64_t slot = ((x >> 32) * s->V) >> 32;
+            const uint64_t pick = ((uint32_t)x < s->alias_prob[slot]) ? slot : s->alias_idx[slot];
+            if (e == 0) u = pick; else v = pick;
         }
         if (s->permute) {
             u = perm_apply(&s->perm, u);
@@ -172,55 +167,115 @@ static void sort_u32(uint32_t *a, uint64_t n)
     }
 }
 
-/* Builds the simple symmetric graph of the sampler's m samples. */
+/* Builds the simple symmetric graph of the sampler's m samples.
+ * 1. every thread draws a fixed contiguous range of samples and counts, per
+ *    bucket of source vertices, the directed pairs it will emit (both
+ *    directions, loops dropped);
+ * 2. the same ranges are drawn again and each pair (src << 32 | dst) is
+ *    written to its bucket's region (one write stream per bucket per thread);
+ * 3. each bucket is counting-sorted by source vertex in cache, and every
+ *    list is sorted and deduplicated.
+ * The result does not depend on the thread count. */
+static inline uint64_t bucket_of(uint64_t x, uint64_t nb, uint64_t V)
+{
+    return (x * nb) / V;
+}
+
 static gg_graph *build(const sampler_t *s)
 {
-    uint64_t V = s->V, m = s->m;
+    const uint64_t V = s->V, m = s->m;
+    uint64_t nb = 1024;
+    while (nb > 1 && V / nb < 64) nb >>= 1;
+    const int T = omp_get_max_threads();
     gg_graph *g = (gg_graph *)calloc(1, sizeof(gg_graph));
-    uint32_t *deg = (uint32_t *)calloc(V, sizeof(uint32_t));
+    uint64_t *cnt = (uint64_t *)calloc((size_t)T * nb, sizeof(uint64_t));
+    uint64_t *bstart = (uint64_t *)calloc(nb + 1, sizeof(uint64_t));
+    uint32_t *deg = (uint32_t *)calloc(V ? V : 1, sizeof(uint32_t));
     uint64_t *off = (uint64_t *)malloc((V + 1) * sizeof(uint64_t));
-    uint64_t *pos = (uint64_t *)malloc(V * sizeof(uint64_t));
-    if (!g || !deg || !off || !pos) goto fail;
+    uint64_t *pairs = NULL;
+    int failed = 0;
+    if (!g || !cnt || !bstart || !deg || !off) goto fail;
+    const int verbose = getenv("GG_VERBOSE") != NULL;
+    double t0 = omp_get_wtime();
 
-#pragma omp parallel for schedule(static, 65536)
-    for (uint64_t k = 0; k < m; ++k) {
-        uint64_t u, v;
-        sample_edge(s, k, &u, &v);
-        if (u == v) continue;
-        __atomic_fetch_add(&deg[u], 1u, __ATOMIC_RELAXED);
-        __atomic_fetch_add(&deg[v], 1u, __ATOMIC_RELAXED);
+#pragma omp parallel num_threads(T)
+    {
+        const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+        uint64_t *c = cnt + (size_t)t * nb;
+        const uint64_t k0 = m * (uint64_t)t / nt, k1 = m * (uint64_t)(t + 1) / nt;
+        for (uint64_t k = k0; k < k1; ++k) {
+            uint64_t u, v;
+            sample_edge(s, k, &u, &v);
+            if (u == v) continue;
+            c[bucket_of(u, nb, V)]++;
+            c[bucket_of(v, nb, V)]++;
+        }
     }
-    off[0] = 0;
-    for (uint64_t v = 0; v < V; ++v) off[v + 1] = off[v] + deg[v];
-    uint64_t total = off[V];
-    g->adj = (uint32_t *)malloc((total ? total : 1) * sizeof(uint32_t));
-    if (!g->adj) goto fail;
-    memcpy(pos, off, V * sizeof(uint64_t));
+    /* positions: bucket-major, thread-minor */
+    {
+        uint64_t run = 0;
+        for (uint64_t b = 0; b < nb; ++b) {
+            bstart[b] = run;
+            for (int t = 0; t < T; ++t) {
+                uint64_t x = cnt[(size_t)t * nb + b];
+                cnt[(size_t)t * nb + b] = run;
+                run += x;
+            }
+        }
+        bstart[nb] = run;
+    }
+    if (verbose) fprintf(stderr, "[gg] count %.2fs\n", omp_get_wtime() - t0);
+    pairs = (uint64_t *)malloc((bstart[nb] ? bstart[nb] : 1) * sizeof(uint64_t));
+    g->adj = (uint32_t *)malloc((bstart[nb] ? bstart[nb] : 1) * sizeof(uint32_t));
+    if (!pairs || !g->adj) goto fail;
 
-#pragma omp parallel for schedule(static, 65536)
-    for (uint64_t k = 0; k < m; ++k) {
-        uint64_t u, v;
-        sample_edge(s, k, &u, &v);
-        if (u == v) continue;
-        uint64_t pu = __atomic_fetch_add(&pos[u], 1ull, __ATOMIC_RELAXED);
-        uint64_t pv = __atomic_fetch_add(&pos[v], 1ull, __ATOMIC_RELAXED);
-        g->adj[pu] = (uint32_t)v;
-        g->adj[pv] = (uint32_t)u;
+#pragma omp parallel num_threads(T)
+    {
+        const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+        uint64_t *pos = cnt + (size_t)t * nb;
+        const uint64_t k0 = m * (uint64_t)t / nt, k1 = m * (uint64_t)(t + 1) / nt;
+        for (uint64_t k = k0; k < k1; ++k) {
+            uint64_t u, v;
+            sample_edge(s, k, &u, &v);
+            if (u == v) continue;
+            pairs[pos[bucket_of(u, nb, V)]++] = (u << 32) | v;
+            pairs[pos[bucket_of(v, nb, V)]++] = (v << 32) | u;
+        }
     }
-    free(pos);
-    pos = NULL;
 
-    /* sort + unique each list in place; deg[v] becomes the unique count */
-#pragma omp parallel for schedule(dynamic, 4096)
-    for (uint64_t v = 0; v < V; ++v) {
-        uint32_t *a = g->adj + off[v];
-        uint64_t n = off[v + 1] - off[v];
-        sort_u32(a, n);
-        uint64_t w = 0;
-        for (uint64_t i = 0; i < n; ++i)
-            if (i == 0 || a[i] != a[w - 1]) a[w++] = a[i];
-        deg[v] = (uint32_t)w;
+    if (verbose) fprintf(stderr, "[gg] scatter %.2fs\n", omp_get_wtime() - t0);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(T)
+    for (uint64_t b = 0; b < nb; ++b) {
+        const uint64_t lo = (b * V + nb - 1) / nb, hi = ((b + 1) * V + nb - 1) / nb;
+        const uint64_t nv = hi - lo, base = bstart[b], n = bstart[b + 1] - base;
+        uint64_t *lstart = (uint64_t *)calloc(nv + 1, sizeof(uint64_t));
+        if (!lstart) {
+            __atomic_store_n(&failed, 1, __ATOMIC_RELAXED);
+            continue;
+        }
+        for (uint64_t i = 0; i < n; ++i) lstart[(pairs[base + i] >> 32) - lo + 1]++;
+        for (uint64_t x = 0; x < nv; ++x) lstart[x + 1] += lstart[x];
+        for (uint64_t x = 0; x < nv; ++x) off[lo + x] = base + lstart[x];
+        for (uint64_t i = 0; i < n; ++i) {
+            uint64_t p = pairs[base + i];
+            g->adj[base + lstart[(p >> 32) - lo]++] = (uint32_t)p;
+        }
+        /* lstart[x] now holds the end of list x */
+        for (uint64_t x = 0; x < nv; ++x) {
+            uint32_t *a = g->adj + off[lo + x];
+            uint64_t len = (base + lstart[x]) - off[lo + x];
+            sort_u32(a, len);
+            uint64_t w = 0;
+            for (uint64_t i = 0; i < len; ++i)
+                if (i == 0 || a[i] != a[w - 1]) a[w++] = a[i];
+            deg[lo + x] = (uint32_t)w;
+        }
+        free(lstart);
     }
+    free(pairs);
+    pairs = NULL;
+    if (verbose) fprintf(stderr, "[gg] buckets %.2fs\n", omp_get_wtime() - t0);
+    if (failed) goto fail;
     g->row_ptr = (uint64_t *)malloc((V + 1) * sizeof(uint64_t));
     if (!g->row_ptr) goto fail;
     g->row_ptr[0] = 0;
@@ -229,10 +284,12 @@ static gg_graph *build(const sampler_t *s)
     g->V = V;
     g->off = off;
     free(deg);
+    free(cnt);
+    free(bstart);
     return g;
 fail:
     if (g) { free(g->adj); free(g->row_ptr); free(g); }
-    free(deg); free(off); free(pos);
+    free(deg); free(off); free(pairs); free(cnt); free(bstart);
     return NULL;
 }
 
@@ -271,22 +328,45 @@ void *gg_chung_lu(uint64_t V, uint64_t samples, double gamma, double i0,
 {
     sampler_t s;
     memset(&s, 0, sizeof(s));
-    double *cdf = (double *)malloc(V * sizeof(double));
-    if (!cdf) return NULL;
-    double acc = 0.0, expo = -1.0 / (gamma - 1.0);
-    for (uint64_t i = 0; i < V; ++i) {
-        acc += pow((double)i + i0, expo);
-        cdf[i] = acc;
+    /* Vose's alias table for weights (i + i0)^(-1/(gamma-1)) */
+    double *pw = (double *)malloc(V * sizeof(double));
+    uint32_t *prob = (uint32_t *)malloc(V * sizeof(uint32_t));
+    uint32_t *alias = (uint32_t *)malloc(V * sizeof(uint32_t));
+    uint32_t *small = (uint32_t *)malloc(V * sizeof(uint32_t));
+    uint32_t *large = (uint32_t *)malloc(V * sizeof(uint32_t));
+    if (!pw || !prob || !alias || !small || !large || V == 0 || V > 0xFFFFFFFFull) {
+        free(pw); free(prob); free(alias); free(small); free(large);
+        return NULL;
     }
+    double total = 0.0, expo = -1.0 / (gamma - 1.0);
+    for (uint64_t i = 0; i < V; ++i) total += (pw[i] = pow((double)i + i0, expo));
+    uint64_t ns = 0, nl = 0;
+    for (uint64_t i = 0; i < V; ++i) {
+        pw[i] = pw[i] * (double)V / total;
+        alias[i] = (uint32_t)i;
+        if (pw[i] < 1.0) small[ns++] = (uint32_t)i; else large[nl++] = (uint32_t)i;
+    }
+    while (ns > 0 && nl > 0) {
+        uint32_t l = small[--ns], gi = large[--nl];
+        prob[l] = (uint32_t)fmin(4294967295.0, pw[l] * 4294967296.0);
+        alias[l] = gi;
+        pw[gi] = (pw[gi] + pw[l]) - 1.0;
+        if (pw[gi] < 1.0) small[ns++] = gi; else large[nl++] = gi;
+    }
+    while (nl > 0) prob[large[--nl]] = 0xFFFFFFFFu;
+    while (ns > 0) prob[small[--ns]] = 0xFFFFFFFFu;
+    free(pw); free(small); free(large);
     s.kind = GG_CHUNGLU;
     s.V = V;
     s.m = samples;
     s.key = gg_stream_key(seed, STREAM_EDGES);
-    s.cdf = cdf;
+    s.alias_prob = prob;
+    s.alias_idx = alias;
     s.permute = permute;
     perm_init(&s.perm, seed, V);
     gg_graph *g = build(&s);
-    free(cdf);
+    free(prob);
+    free(alias);
     return g;
 }
 
@@ -371,6 +451,61 @@ int gg_relabel(void *h, const uint64_t *new_id)
     g->row_ptr = rp;
     g->adj = adj;
     memcpy(g->off, rp, V * sizeof(uint64_t));
+    return 0;
+}
+
+/* Locality order for the power-law stand-in of crawled graphs: ids are given
+ * in first-visit order of a queue walk from the highest-degree vertex
+ * (unreached vertices follow in id order), then runs of `run` consecutive new
+ * ids are permuted by a seeded Fisher-Yates shuffle (order inside a run kept).
+ * Writes new_id[old] (a bijection). */
+int gg_locality_order(void *h, uint64_t run, uint64_t seed, uint64_t *new_id)
+{
+    gg_graph *g = (gg_graph *)h;
+    const uint64_t V = g->V;
+    uint64_t *order = (uint64_t *)malloc((V ? V : 1) * sizeof(uint64_t));
+    unsigned char *seen = (unsigned char *)calloc(V ? V : 1, 1);
+    if (!order || !seen || run == 0) { free(order); free(seen); return -2; }
+    uint64_t root = 0, best = 0, tail = 0, head = 0;
+    for (uint64_t v = 0; v < V; ++v)
+        if (g->row_ptr[v + 1] - g->row_ptr[v] > best) { best = g->row_ptr[v + 1] - g->row_ptr[v]; root = v; }
+    for (uint64_t start = 0; start <= V; ++start) {
+        uint64_t s = start == 0 ? root : start - 1;
+        if (V == 0 || seen[s]) continue;
+        seen[s] = 1;
+        order[tail++] = s;
+        while (head < tail) {
+            uint64_t u = order[head++];
+            const uint32_t *a = g->adj + g->off[u];
+            for (uint64_t i = 0; i < g->row_ptr[u + 1] - g->row_ptr[u]; ++i)
+                if (!seen[a[i]]) { seen[a[i]] = 1; order[tail++] = a[i]; }
+        }
+    }
+    free(seen);
+    /* shuffle whole runs: new position of run r is runperm[r] */
+    const uint64_t nruns = (V + run - 1) / run;
+    uint64_t *runperm = (uint64_t *)malloc((nruns ? nruns : 1) * sizeof(uint64_t));
+    if (!runperm) { free(order); return -2; }
+    for (uint64_t r = 0; r < nruns; ++r) runperm[r] = r;
+    const uint64_t key = gg_stream_key(seed, 4);
+    for (uint64_t r = nruns; r > 1; --r) {
+        uint64_t j = draw(key, r) % r, t = runperm[r - 1];
+        runperm[r - 1] = runperm[j];
+        runperm[j] = t;
+    }
+    /* the last run may be short: lay runs out in permuted order */
+    uint64_t *start = (uint64_t *)malloc((nruns + 1) * sizeof(uint64_t));
+    if (!start) { free(order); free(runperm); return -2; }
+    uint64_t pos = 0;
+    for (uint64_t k = 0; k < nruns; ++k) {
+        uint64_t r = runperm[k];
+        start[r] = pos;
+        pos += (r + 1) * run <= V ? run : V - r * run;
+    }
+    for (uint64_t i = 0; i < V; ++i) new_id[order[i]] = start[i / run] + i % run;
+    free(start);
+    free(runperm);
+    free(order);
     return 0;
 }
 

@@ -80,6 +80,11 @@ typedef enum {
 #define EMOGI_SCHED_HEURISTIC 16        /* rule of thumb on frontier size and degrees */
 #define EMOGI_SCHED_LEARNED 17          /* MLP over frontier features (falls back to the
                                            heuristic when no weights are loaded)       */
+#define EMOGI_SCHED_PROBE 18            /* time all six variants on every level (state is
+                                           saved and restored), then run the fastest: the
+                                           per-level best that training labels come from */
+#define EMOGI_SCHED_RECORD 0x100        /* OR into any mode: keep each level's 16 features */
+#define EMOGI_NUM_FEATURES 16
 
 #define EMOGI_MAX_LEVEL_STATS 512
 
@@ -99,7 +104,32 @@ typedef struct {
     uint32_t level_frontier[EMOGI_MAX_LEVEL_STATS];
     float level_ms[EMOGI_MAX_LEVEL_STATS];   /* neighbour-scan kernel time per level     */
     uint64_t level_edges[EMOGI_MAX_LEVEL_STATS]; /* edges scanned per level               */
+    /* frontier features per level (EMOGI_SCHED_RECORD): log2(1+|F|)/32, |F|/V,
+     * log2(1+sum deg)/40, sum deg/E, fractions of frontier degrees in <=1, [2,4),
+     * [4,8), [8,16), [16,64), [64,256), [256,4096), >=4096, 8-byte ids, weights
+     * read, zero-copy placement, managed placement */
+    float level_features[EMOGI_MAX_LEVEL_STATS][EMOGI_NUM_FEATURES];
+    float level_probe_ms[EMOGI_MAX_LEVEL_STATS][EMOGI_NUM_VARIANTS]; /* EMOGI_SCHED_PROBE */
 } emogi_stats_t;
+
+/* ---- host-link calibration (the MI355X counterpart of the paper's toy 1-D
+ *      zero-copy copy study, Sec. 3.3 and Fig. 4) ---- */
+#define EMOGI_CALIB_BLOCKS 8 /* random-read block sizes 32, 64, ..., 4096 bytes */
+typedef struct {
+    double memcpy_GBps;        /* hipMemcpy pinned host -> device, best of 3 (Sec. 5.3.2's peak) */
+    double seq_read_GBps[3];   /* wave-merged sequential kernel reads, 4/8/16-byte lanes        */
+    uint32_t block_bytes[EMOGI_CALIB_BLOCKS];
+    double rand_aligned_GBps[EMOGI_CALIB_BLOCKS]; /* random blocks starting on a block boundary  */
+    double rand_shift32_GBps[EMOGI_CALIB_BLOCKS]; /* the same blocks shifted by 32 bytes        */
+    uint32_t request_unit;     /* R: smallest aligned block reaching 90% of the sequential rate  */
+    double latency_us;         /* dependent-load round trip to pinned host memory                */
+    uint64_t buffer_bytes;     /* size of the pinned buffer used                                 */
+} emogi_link_profile_t;
+
+/* Measures the host link with a pinned buffer of `bytes` (>= 64 MiB; a few GiB
+ * recommended) on the current device and null stream.  Allocates and frees its
+ * own memory.  EMOGI_E_OOM_* when the buffers cannot be allocated. */
+emogi_status_t emogi_calibrate_link(size_t bytes, emogi_link_profile_t *out);
 
 /* ---- pinned host memory for EMOGI_F_BORROW (Sec. 3.1: the edge list must be
  *      pinned and mapped into the GPU's address space) ---- */
@@ -134,6 +164,36 @@ emogi_status_t emogi_set_scheduler(emogi_graph_t g, int mode);
  * from host memory; NULL clears them (learned mode then uses the heuristic). */
 emogi_status_t emogi_set_scheduler_weights(emogi_graph_t g, const float *params, size_t count);
 
+/* ---- scheduler network training (16 -> 64 -> 64 -> 6, ReLU, softmax
+ *      cross-entropy, Adam; fp32 HIP kernels).  The worker-size trade-off of
+ *      Sec. 4.3.1 and the GK/GU contrast of Sec. 5.3.1 motivate choosing the
+ *      variant per level; the network is trained on per-level timings. ----
+ * Device-pointer primitives (all arrays hipMalloc'd, row-major):
+ *   params float[5638] (W1[64][16], b1[64], W2[64][64], b2[64], W3[6][64], b3[6]),
+ *   X float[B][16], y int32[B] in 0..5, Z float[B][6], grad float[5638],
+ *   loss float[1] (mean over the batch; may be NULL). */
+emogi_status_t emogi_mlp_forward(const float *params, const float *X, uint32_t B, float *Z,
+                                 void *stream);
+emogi_status_t emogi_mlp_loss_grad(const float *params, const float *X, const int32_t *y,
+                                   uint32_t B, float *grad, float *loss, void *stream);
+/* One Adam step in place (m, v: float[5638] moment buffers; t counts from 1). */
+emogi_status_t emogi_mlp_adam_step(float *params, const float *grad, float *m, float *v,
+                                   uint32_t t, float lr, float beta1, float beta2, float eps,
+                                   void *stream);
+typedef struct {
+    float lr, beta1, beta2, eps;
+    uint32_t batch;   /* minibatch size */
+    uint32_t epochs;
+    uint64_t seed;    /* shuffling */
+} emogi_train_config_t;
+/* Whole training run on the GPU from host arrays: X float[N][16], y int32[N];
+ * params (host, 5638 floats) holds the initial weights and receives the
+ * trained ones; loss_history (host, `epochs` floats, may be NULL) gets the mean
+ * minibatch loss per epoch.  Only full minibatches are used. */
+emogi_status_t emogi_mlp_train(const float *X, const int32_t *y, uint32_t N,
+                               const emogi_train_config_t *cfg, float *params,
+                               float *loss_history);
+
 /* ---- traversals (Sec. 5.1: BFS, SSSP, CC) ----
  * emogi_bfs : levels[v] = fewest edges on a path src->v (src gets 0).
  * emogi_sssp: dist[v] = least sum of weights over paths src->v; needs weights;
@@ -145,6 +205,39 @@ emogi_status_t emogi_set_scheduler_weights(emogi_graph_t g, const float *params,
 emogi_status_t emogi_bfs(emogi_graph_t g, uint64_t src, uint32_t *levels, void *stream);
 emogi_status_t emogi_sssp(emogi_graph_t g, uint64_t src, uint32_t *dist, void *stream);
 emogi_status_t emogi_cc(emogi_graph_t g, uint32_t *labels, void *stream);
+
+/* ---- batched multi-source traversal (the paper runs 64 sources per graph,
+ *      Sec. 5.2; here up to 64 run together and each list read from host
+ *      memory serves every source active at that vertex) ----
+ * srcs     host uint64[n], 1 <= n <= 64, each < V (repeats allowed).
+ * out      device uint32[n * V], source-major: out[s * V + v].
+ * BFS gives levels, SSSP distances (weights required), per source exactly as
+ * emogi_bfs / emogi_sssp would.  Level steps are captured in hipGraphs and
+ * replayed on a private stream; the call returns when all sources finish. */
+typedef struct {
+    uint32_t hub_degree;      /* lists longer than this are scanned by a whole workgroup */
+    uint32_t steps_per_graph; /* level steps per hipGraph replay (even, 2..32)             */
+    uint32_t blocks_per_cu;   /* grid = 256 * blocks_per_cu workgroups (1..8)             */
+    uint32_t use_graph;       /* 1: capture + replay hipGraphs, 0: launch steps directly   */
+} emogi_batch_params_t;
+
+emogi_status_t emogi_bfs_batch(emogi_graph_t g, const uint64_t *srcs, uint32_t n, uint32_t *out,
+                               void *stream);
+emogi_status_t emogi_sssp_batch(emogi_graph_t g, const uint64_t *srcs, uint32_t n, uint32_t *out,
+                                void *stream);
+emogi_status_t emogi_set_batch_params(emogi_graph_t g, const emogi_batch_params_t *p);
+emogi_status_t emogi_get_batch_params(emogi_graph_t g, emogi_batch_params_t *p);
+/* Autotuner: runs the batched traversal (algo 0 = BFS, 1 = SSSP) for each
+ * candidate parameter set, keeps the fastest on the handle and returns it.
+ * `out` is scratch of n * V uint32 (device) and holds the last result.
+ * `table` (may be NULL) receives up to `table_len` (params, ms) pairs. */
+typedef struct {
+    emogi_batch_params_t params;
+    float ms;
+} emogi_batch_trial_t;
+emogi_status_t emogi_autotune_batch(emogi_graph_t g, int algo, const uint64_t *srcs, uint32_t n,
+                                    uint32_t *out, void *stream, emogi_batch_params_t *best,
+                                    emogi_batch_trial_t *table, uint32_t table_len);
 
 /* Statistics of the last traversal on this handle. */
 emogi_status_t emogi_last_stats(emogi_graph_t g, emogi_stats_t *out);

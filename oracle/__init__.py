@@ -40,7 +40,7 @@ def build(force=False):
     ):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-Wall", "-Werror", "-shared", "-fPIC",
+            ["gcc", "-O2", "-std=gnu99", "-fopenmp", "-Wall", "-Werror", "-shared", "-fPIC",
              _SRC, "-o", tmp]
         )
         os.replace(tmp, _LIB_PATH)

@@ -297,20 +297,32 @@ int oracle_certify_distances(uint64_t V, const uint64_t *row_ptr,
     unsigned char *tight = (unsigned char *)calloc(V ? V : 1, 1);
     if (!tight) return -2;
     int rc = 0;
-    for (uint64_t u = 0; u < V && !rc; ++u) {
+    /* The loops are independent per vertex; they run on all cores so the
+     * check stays affordable on billions of edges.  Failure codes combine
+     * with max (-1 < 2 < 3 never mix: each is reported alone below). */
+    int bad_weight = 0, bad_edge = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(| : bad_weight, bad_edge)
+    for (uint64_t u = 0; u < V; ++u) {
         if (d[u] == ORC_INF32) continue;
         for (uint64_t i = row_ptr[u]; i < row_ptr[u + 1]; ++i) {
             uint64_t v = col_at(col, col_bytes, i);
             uint64_t c = w ? (uint64_t)w[i] : 1;
-            if (c == 0) { rc = -1; break; }
+            if (c == 0) { bad_weight = 1; break; }
             uint64_t nd = (uint64_t)d[u] + c;
             uint64_t dv = d[v] == ORC_INF32 ? ORC_INF64 : (uint64_t)d[v];
-            if (dv > nd) { rc = 2; break; }
-            if (dv == nd) tight[v] = 1;
+            if (dv > nd) { bad_edge = 1; break; }
+            if (dv == nd) __atomic_store_n(&tight[v], 1, __ATOMIC_RELAXED);
         }
     }
-    for (uint64_t v = 0; v < V && !rc; ++v)
-        if (v != src && d[v] != ORC_INF32 && !tight[v]) rc = 3;
+    if (bad_weight) rc = -1;
+    else if (bad_edge) rc = 2;
+    if (!rc) {
+        int untight = 0;
+#pragma omp parallel for reduction(| : untight)
+        for (uint64_t v = 0; v < V; ++v)
+            if (v != src && d[v] != ORC_INF32 && !tight[v]) untight = 1;
+        if (untight) rc = 3;
+    }
     free(tight);
     return rc;
 }

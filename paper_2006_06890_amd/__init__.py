@@ -6,4 +6,5 @@ in pinned host memory and is read in place by the GPU, through the C ABI of
 """
 from .emogi import (  # noqa: F401
     EmogiError, Graph, PinnedArray, Stats, VARIANTS, INF, N_SCHED_PARAMS, lib, to_u32,
+    calibrate_link,
 )

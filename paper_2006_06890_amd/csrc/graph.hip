@@ -130,7 +130,18 @@ static void release(emogi_graph_s *g) {
     if (p.host_counters) (void)hipHostFree(p.host_counters);
     if (p.features) (void)hipFree(p.features);
     if (p.degree_hist) (void)hipFree(p.degree_hist);
+    for (void *x : {(void *)p.snap_state, (void *)p.snap_stamp, (void *)p.snap_bitmap})
+        if (x) (void)hipFree(x);
     if (g->mlp_params) (void)hipFree(g->mlp_params);
+    BatchPool &b = g->batch;
+    for (int i = 0; i < 2; ++i) {
+        if (b.mask[i]) (void)hipFree(b.mask[i]);
+        if (b.hub[i]) (void)hipFree(b.hub[i]);
+    }
+    for (void *x : {(void *)b.vis, (void *)b.ovf, (void *)b.dist, (void *)b.ctr, (void *)b.srcs})
+        if (x) (void)hipFree(x);
+    if (b.host_ctr) (void)hipHostFree(b.host_ctr);
+    if (b.stream) (void)hipStreamDestroy(b.stream);
     for (hipEvent_t e : {g->ev_begin, g->ev_end, g->ev_k0, g->ev_k1})
         if (e) (void)hipEventDestroy(e);
     delete g;
@@ -350,12 +361,14 @@ emogi_status_t emogi_set_request_unit(emogi_graph_t g, uint32_t bytes) {
 }
 
 emogi_status_t emogi_set_scheduler(emogi_graph_t g, int mode) {
-    if (!g || !((mode >= 0 && mode < EMOGI_NUM_VARIANTS) || mode == EMOGI_SCHED_HEURISTIC ||
-                mode == EMOGI_SCHED_LEARNED)) {
+    const int base = mode & ~int(EMOGI_SCHED_RECORD);
+    if (!g || !((base >= 0 && base < EMOGI_NUM_VARIANTS) || base == EMOGI_SCHED_HEURISTIC ||
+                base == EMOGI_SCHED_LEARNED || base == EMOGI_SCHED_PROBE)) {
         set_error("unknown scheduler mode %d", mode);
         return EMOGI_E_INVALID;
     }
-    g->sched_mode = mode;
+    g->sched_mode = base;
+    g->record_features = (mode & EMOGI_SCHED_RECORD) != 0;
     return EMOGI_OK;
 }
 

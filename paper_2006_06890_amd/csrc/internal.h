@@ -44,7 +44,23 @@ struct Pool {
     unsigned long long *host_counters = nullptr; // pinned mirror
     float *features = nullptr;                // scheduler features (device)
     uint32_t *degree_hist = nullptr;          // scheduler degree histogram (device)
+    uint32_t *snap_state = nullptr;           // probe mode: saved state of a level
+    uint32_t *snap_stamp = nullptr;
+    uint32_t *snap_bitmap = nullptr;
     size_t chunk_cap = 0;
+};
+
+// State of batched multi-source traversals (up to 64 sources, one bit each).
+struct BatchPool {
+    unsigned long long *mask[2] = {nullptr, nullptr}; // frontier masks (current / next) per vertex
+    unsigned long long *vis = nullptr;    // BFS: sources that reached v
+    unsigned long long *ovf = nullptr;    // SSSP: sources whose relaxation into v overflowed
+    uint32_t *dist = nullptr;             // SSSP: distances, vertex-major [V][64]
+    uint32_t *hub[2] = {nullptr, nullptr};// queues of long lists (workgroup per vertex)
+    unsigned long long *ctr = nullptr;    // queue lengths, level, flags
+    unsigned long long *host_ctr = nullptr;
+    uint64_t *srcs = nullptr;             // device copy of the sources
+    hipStream_t stream = nullptr;         // private stream for capture and replay
 };
 
 }  // namespace emogi
@@ -64,10 +80,13 @@ struct emogi_graph_s {
 
     uint32_t request_unit = 256;
     int sched_mode = EMOGI_SCHED_HEURISTIC;
+    bool record_features = false;  // store per-level frontier features in the stats
     float *mlp_params = nullptr;   // device, 5638 floats, or null
     uint64_t max_degree = 0;
 
     emogi::Pool pool;
+    emogi::BatchPool batch;
+    emogi_batch_params_t batch_params{1024, 4, 8, 1};
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;
     emogi_stats_t stats{};

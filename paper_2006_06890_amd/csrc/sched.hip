@@ -154,13 +154,18 @@ static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *
     return h.choice;
 }
 
-int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue, hipStream_t stream) {
+// Variant for the level; fills `features` (16 floats) when non-null.
+// Returns -1 when the scheduler's kernels fail.
+int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue, hipStream_t stream,
+                   float *features) {
     const int m = g->sched_mode;
-    if (m >= 0 && m < EMOGI_NUM_VARIANTS) return m;
-    if (m == EMOGI_SCHED_LEARNED && g->mlp_params) {
-        int v = learned_pick(g, algo, n, queue, stream, nullptr);
-        if (v >= 0) return v;
+    int learned = -2;
+    if (features || (m == EMOGI_SCHED_LEARNED && g->mlp_params)) {
+        learned = learned_pick(g, algo, n, queue, stream, features);
+        if (learned < 0) return -1;
     }
+    if (m >= 0 && m < EMOGI_NUM_VARIANTS) return m;
+    if (m == EMOGI_SCHED_LEARNED && g->mlp_params) return learned;
     return heuristic_variant(g, n);
 }
 

@@ -20,6 +20,7 @@
 //  * vertex state (levels, distances, labels, visited bitmap, stamps) stays
 //    in HBM; only the edge list (and weights) cross the host link.
 #include "internal.h"
+#include "wave.h"
 
 #include <algorithm>
 #include <cstdlib>
@@ -30,97 +31,15 @@ namespace emogi {
 
 enum Algo { A_BFS = 0, A_SSSP = 1, A_CC = 2 };
 
-constexpr int kWave = 64;
-constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kSegCap = 512;      // LDS staging entries per wave
 constexpr int kUnroll = 4;        // loads in flight per lane in the wave variants
 constexpr int kChunksPerWave = 8; // V5: consecutive aligned chunks per wave visit
 constexpr int kMaxGrid = 256 * 8; // 8 blocks of 4 waves on each of the 256 CUs
 
-// ---------------------------------------------------------------------------
-// wave helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int lane_id() {
-    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-// Number of set bits of m below this lane.
-__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-}
-__device__ __forceinline__ uint32_t uniform32(uint32_t x) {
-    return __builtin_amdgcn_readfirstlane(x);
-}
-__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
-    uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(x));
-    uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(x >> 32));
-    return (uint64_t(hi) << 32) | lo;
-}
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
-    for (int o = 32; o > 0; o >>= 1) {
-        uint32_t lo = __shfl_xor(uint32_t(x), o), hi = __shfl_xor(uint32_t(x >> 32), o);
-        x += (uint64_t(hi) << 32) | lo;
-    }
-    return x;
-}
-
-template <class ColT>
-__device__ __forceinline__ uint32_t load_col(const ColT *col, uint64_t i) {
-    return uint32_t(col[i]);
-}
-
-// ---------------------------------------------------------------------------
-// Per-wave LDS staging of next-frontier entries.
-// All 64 lanes must call stage()/flush() together (uniform control flow).
-// ---------------------------------------------------------------------------
-struct Stage {
-    uint32_t *seg;  // this wave's LDS segment
-    uint32_t cnt;   // entries staged (same value in every lane)
-};
-
-__device__ __forceinline__ void flush(Stage &st, uint32_t *next, unsigned long long *ctr, int lane) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    uint32_t base = 0;
-    if (lane == 0) base = uint32_t(atomicAdd(&ctr[C_NEXT], (unsigned long long)st.cnt));
-    base = __shfl(base, 0);
-    for (uint32_t i = lane; i < st.cnt; i += kWave) next[base + i] = st.seg[i];
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    st.cnt = 0;
-}
-
-__device__ __forceinline__ void stage(Stage &st, bool push, uint32_t v, uint32_t *next,
-                                      unsigned long long *ctr, int lane) {
-    uint64_t m = __ballot(push);
-    if (m == 0) return;
-    uint32_t c = uint32_t(__popcll(m));
-    if (st.cnt + c > uint32_t(kSegCap)) flush(st, next, ctr, lane);
-    if (push) st.seg[st.cnt + rank_below(m)] = v;
-    st.cnt += c;
-}
-
-// End of a block: one global reservation for all staged entries, then the
-// waves copy their segments out; also folds the statistics.
+// End of a scan block: flush the staged frontier and fold the statistics.
 __device__ __forceinline__ void finish_block(Stage &st, uint32_t *next, unsigned long long *ctr,
                                              int lane, int wid, uint64_t edges, uint64_t reqb,
                                              uint64_t verts) {
-    __shared__ uint32_t s_cnt[kWavesPerBlock];
-    __shared__ uint32_t s_off[kWavesPerBlock];
-    __shared__ uint32_t s_base;
-    if (lane == 0) s_cnt[wid] = st.cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tot = 0;
-        for (int w = 0; w < kWavesPerBlock; ++w) {
-            s_off[w] = tot;
-            tot += s_cnt[w];
-        }
-        s_base = tot ? uint32_t(atomicAdd(&ctr[C_NEXT], (unsigned long long)tot)) : 0u;
-    }
-    __syncthreads();
-    uint32_t base = s_base + s_off[wid];
-    for (uint32_t i = lane; i < st.cnt; i += kWave) next[base + i] = st.seg[i];
+    finish_queue(st, next, &ctr[C_NEXT], lane, wid);
     edges = wave_sum64(edges);
     reqb = wave_sum64(reqb);
     verts = wave_sum64(verts);
@@ -244,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s, OpArgs a) {
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
                 const bool p = ok[k] && visit<A>(a, uval, v[k], w[k]);
-                stage(st, p, v[k], s.next, a.ctr, lane);
+                stage(st, p, v[k], s.next, &a.ctr[C_NEXT], lane);
             }
         }
     }
@@ -289,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_block(ScanArgs s, OpArgs a) {
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 const bool p = ok[k] && visit<A>(a, uval, v[k], w[k]);
-                stage(st, p, v[k], s.next, a.ctr, lane);
+                stage(st, p, v[k], s.next, &a.ctr[C_NEXT], lane);
             }
         }
     }
@@ -339,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_group(ScanArgs s, OpArgs a) {
                 if (A == A_SSSP) w = s.w[j];
             }
             const bool p = ok && visit<A>(a, uval, v, w);
-            stage(st, p, v, s.next, a.ctr, lane);
+            stage(st, p, v, s.next, &a.ctr[C_NEXT], lane);
         }
     }
     finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts);
@@ -424,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s, OpArgs a) {
 #pragma unroll
             for (int i = 0; i < kUnroll; ++i) {
                 const bool p = ok[i] && visit<A>(a, uv[i], v[i], w[i]);
-                stage(st, p, v[i], s.next, a.ctr, lane);
+                stage(st, p, v[i], s.next, &a.ctr[C_NEXT], lane);
             }
         }
     }
@@ -638,7 +557,32 @@ int heuristic_variant(const emogi_graph_s *g, uint64_t n) {
     return EMOGI_V3_WAVE_ALIGNED;
 }
 
-int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue, hipStream_t stream);
+int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue, hipStream_t stream,
+                   float *features);
+
+// Probe mode: save (restore=false) or restore (restore=true) the state a
+// level step modifies, so every variant can be timed on the same level.
+static emogi_status_t snapshot(emogi_graph_s *g, int algo, uint32_t *out, hipStream_t stream,
+                               bool restore) {
+    Pool &p = g->pool;
+    const uint64_t V = std::max<uint64_t>(g->V, 1), words = (V + 31) / 32;
+    if (!p.snap_state) {
+        if (hipMalloc(&p.snap_state, V * 4) != hipSuccess || hipMalloc(&p.snap_stamp, V * 4) != hipSuccess ||
+            hipMalloc(&p.snap_bitmap, words * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("probe snapshot allocation failed");
+            return EMOGI_E_OOM_DEVICE;
+        }
+    }
+    auto cp = [&](void *live, void *snap, size_t bytes) {
+        return restore ? hipMemcpyAsync(live, snap, bytes, hipMemcpyDeviceToDevice, stream)
+                       : hipMemcpyAsync(snap, live, bytes, hipMemcpyDeviceToDevice, stream);
+    };
+    EMOGI_HIP_TRY(cp(out, p.snap_state, V * 4), EMOGI_E_HIP);
+    if (algo != A_CC) EMOGI_HIP_TRY(cp(p.bitmap, p.snap_bitmap, words * 4), EMOGI_E_HIP);
+    if (algo != A_BFS) EMOGI_HIP_TRY(cp(p.stamp, p.snap_stamp, V * 4), EMOGI_E_HIP);
+    return EMOGI_OK;
+}
 
 static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_t *out,
                                hipStream_t stream) {
@@ -713,54 +657,84 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             return EMOGI_E_NOCONVERGE;
         }
         const uint32_t *queue = identity ? nullptr : p.queue[cur];
-        const int var = choose_variant(g, algo, n, queue, stream);
-        ScanArgs s;
-        s.queue = queue;
-        s.n = uint32_t(n);
-        s.row_ptr = g->row_ptr;
-        s.col = g->col;
-        s.w = g->weights;
-        s.next = p.queue[identity ? 0 : cur ^ 1];
-        s.align_mask = uint64_t(align_elems) - 1;
-        s.req_unit = g->request_unit;
-        s.col_bytes = g->col_bytes;
-        s.chunk_scan = nullptr;
-        OpArgs a;
-        a.state = out;
-        a.bitmap = p.bitmap;
-        a.stamp = p.stamp;
-        a.tag = iter + 1;  // BFS: level of the next frontier; SSSP/CC: round
-        a.V = uint32_t(V);
-        a.ctr = p.counters;
-        EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
-                      EMOGI_E_HIP);
-        if (var == EMOGI_V5_BALANCED) {
-            if ((st = ensure_scan(g, n)) != EMOGI_OK) return st;
-            const unsigned nb = unsigned((n + kScanTile) / kScanTile);  // covers entry n too
-            hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums);
-            hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nb);
-            hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums,
-                               p.chunk_scan);
-            s.chunk_scan = p.chunk_scan;
+        // One level with variant `v`: counters cleared, (V5) chunk scan, the
+        // scan kernel between two events, counters copied back, host waits.
+        auto run_level = [&](int v, float *ms_out) -> emogi_status_t {
+            ScanArgs s;
+            s.queue = queue;
+            s.n = uint32_t(n);
+            s.row_ptr = g->row_ptr;
+            s.col = g->col;
+            s.w = g->weights;
+            s.next = p.queue[identity ? 0 : cur ^ 1];
+            s.align_mask = uint64_t(align_elems) - 1;
+            s.req_unit = g->request_unit;
+            s.col_bytes = g->col_bytes;
+            s.chunk_scan = nullptr;
+            OpArgs a;
+            a.state = out;
+            a.bitmap = p.bitmap;
+            a.stamp = p.stamp;
+            a.tag = iter + 1;  // BFS: level of the next frontier; SSSP/CC: round
+            a.V = uint32_t(V);
+            a.ctr = p.counters;
+            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
+                          EMOGI_E_HIP);
+            if (v == EMOGI_V5_BALANCED) {
+                emogi_status_t e2 = ensure_scan(g, n);
+                if (e2 != EMOGI_OK) return e2;
+                const unsigned nb = unsigned((n + kScanTile) / kScanTile);  // covers entry n too
+                hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums);
+                hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nb);
+                hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums,
+                                   p.chunk_scan);
+                s.chunk_scan = p.chunk_scan;
+            }
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
+            const int key = algo * 2 + (g->col_bytes == 8 ? 1 : 0);
+            switch (key) {
+            case 0: launch_variant<uint32_t, A_BFS>(v, s, a, stream); break;
+            case 1: launch_variant<uint64_t, A_BFS>(v, s, a, stream); break;
+            case 2: launch_variant<uint32_t, A_SSSP>(v, s, a, stream); break;
+            case 3: launch_variant<uint64_t, A_SSSP>(v, s, a, stream); break;
+            case 4: launch_variant<uint32_t, A_CC>(v, s, a, stream); break;
+            default: launch_variant<uint64_t, A_CC>(v, s, a, stream); break;
+            }
+            EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipEventElapsedTime(ms_out, g->ev_k0, g->ev_k1), EMOGI_E_HIP);
+            return EMOGI_OK;
+        };
+        float feats[16];
+        const bool want_feats = g->record_features && iter < EMOGI_MAX_LEVEL_STATS;
+        int var = choose_variant(g, algo, n, queue, stream, want_feats ? feats : nullptr);
+        if (var < 0) {
+            set_error("scheduler kernels failed");
+            return EMOGI_E_HIP;
         }
-        EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
-        const int key = algo * 2 + (g->col_bytes == 8 ? 1 : 0);
-        switch (key) {
-        case 0: launch_variant<uint32_t, A_BFS>(var, s, a, stream); break;
-        case 1: launch_variant<uint64_t, A_BFS>(var, s, a, stream); break;
-        case 2: launch_variant<uint32_t, A_SSSP>(var, s, a, stream); break;
-        case 3: launch_variant<uint64_t, A_SSSP>(var, s, a, stream); break;
-        case 4: launch_variant<uint32_t, A_CC>(var, s, a, stream); break;
-        default: launch_variant<uint64_t, A_CC>(var, s, a, stream); break;
+        if (want_feats) memcpy(S.level_features[iter], feats, sizeof(feats));
+        if (g->sched_mode == EMOGI_SCHED_PROBE) {
+            // Time every variant on the same level state, then run the fastest.
+            if ((st = snapshot(g, algo, out, stream, false)) != EMOGI_OK) return st;
+            float best = 1e30f;
+            for (int v = 0; v < EMOGI_NUM_VARIANTS; ++v) {
+                if (v > 0 && (st = snapshot(g, algo, out, stream, true)) != EMOGI_OK) return st;
+                float pm = 0.f;
+                if ((st = run_level(v, &pm)) != EMOGI_OK) return st;
+                if (iter < EMOGI_MAX_LEVEL_STATS) S.level_probe_ms[iter][v] = pm;
+                if (pm < best) {
+                    best = pm;
+                    var = v;
+                }
+            }
+            if ((st = snapshot(g, algo, out, stream, true)) != EMOGI_OK) return st;
         }
-        EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
-        EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
-        EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
-                                     hipMemcpyDeviceToHost, stream),
-                      EMOGI_E_HIP);
-        EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
         float ms = 0.f;
-        EMOGI_HIP_TRY(hipEventElapsedTime(&ms, g->ev_k0, g->ev_k1), EMOGI_E_HIP);
+        if ((st = run_level(var, &ms)) != EMOGI_OK) return st;
         const unsigned long long *hc = p.host_counters;
         if (iter < EMOGI_MAX_LEVEL_STATS) {
             S.level_variant[iter] = uint8_t(var);

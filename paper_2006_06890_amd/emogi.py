@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libemogi.so")
 
 PLACEMENTS = {"hbm": 0, "host_zero_copy": 1, "managed": 2}
 F_SYMMETRIC, F_VALIDATE, F_BORROW, F_PIN_NONCOHERENT = 0x1, 0x2, 0x4, 0x8
-SCHED_HEURISTIC, SCHED_LEARNED = 16, 17
+SCHED_HEURISTIC, SCHED_LEARNED, SCHED_PROBE, SCHED_RECORD = 16, 17, 18, 0x100
 VARIANTS = ["V0_thread", "V1_group16", "V2_wave", "V3_wave_aligned", "V4_block", "V5_balanced"]
 N_SCHED_PARAMS = 5638
 INF = 0xFFFFFFFF
@@ -50,6 +50,8 @@ class Stats(ctypes.Structure):
         ("level_frontier", ctypes.c_uint32 * MAX_LEVEL_STATS),
         ("level_ms", ctypes.c_float * MAX_LEVEL_STATS),
         ("level_edges", ctypes.c_uint64 * MAX_LEVEL_STATS),
+        ("level_features", (ctypes.c_float * 16) * MAX_LEVEL_STATS),
+        ("level_probe_ms", (ctypes.c_float * 6) * MAX_LEVEL_STATS),
     ]
 
     def as_dict(self):
@@ -69,7 +71,97 @@ class Stats(ctypes.Structure):
             "level_frontier": list(self.level_frontier[:n]),
             "level_ms": list(self.level_ms[:n]),
             "level_edges": list(self.level_edges[:n]),
+            "level_features": [list(self.level_features[i]) for i in range(n)],
+            "level_probe_ms": [list(self.level_probe_ms[i]) for i in range(n)],
         }
+
+
+CALIB_BLOCKS = 8
+
+
+class LinkProfile(ctypes.Structure):
+    _fields_ = [
+        ("memcpy_GBps", ctypes.c_double),
+        ("seq_read_GBps", ctypes.c_double * 3),
+        ("block_bytes", ctypes.c_uint32 * CALIB_BLOCKS),
+        ("rand_aligned_GBps", ctypes.c_double * CALIB_BLOCKS),
+        ("rand_shift32_GBps", ctypes.c_double * CALIB_BLOCKS),
+        ("request_unit", ctypes.c_uint32),
+        ("latency_us", ctypes.c_double),
+        ("buffer_bytes", ctypes.c_uint64),
+    ]
+
+    def as_dict(self):
+        return {
+            "memcpy_GBps": self.memcpy_GBps,
+            "seq_read_GBps": dict(zip((4, 8, 16), list(self.seq_read_GBps))),
+            "rand_aligned_GBps": dict(zip(list(self.block_bytes), list(self.rand_aligned_GBps))),
+            "rand_shift32_GBps": dict(zip(list(self.block_bytes), list(self.rand_shift32_GBps))),
+            "request_unit": self.request_unit,
+            "latency_us": self.latency_us,
+            "buffer_bytes": self.buffer_bytes,
+        }
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [
+        ("hub_degree", ctypes.c_uint32),
+        ("steps_per_graph", ctypes.c_uint32),
+        ("blocks_per_cu", ctypes.c_uint32),
+        ("use_graph", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchTrial(ctypes.Structure):
+    _fields_ = [("params", BatchParams), ("ms", ctypes.c_float)]
+
+
+class TrainConfig(ctypes.Structure):
+    _fields_ = [
+        ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float), ("batch", ctypes.c_uint32), ("epochs", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+def mlp_forward(params, X, stream=None):
+    """Logits [B,6] of the scheduler network; params/X are float32 device tensors."""
+    import torch
+    B = X.shape[0]
+    Z = torch.empty((B, 6), dtype=torch.float32, device=X.device)
+    check(lib().emogi_mlp_forward(params.data_ptr(), X.data_ptr(), B, Z.data_ptr(),
+                                  _stream_handle(stream)))
+    return Z
+
+
+def mlp_loss_grad(params, X, y, stream=None):
+    """(mean cross-entropy loss, gradient[5638]) from the HIP kernels."""
+    import torch
+    grad = torch.empty(N_SCHED_PARAMS, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    check(lib().emogi_mlp_loss_grad(params.data_ptr(), X.data_ptr(), y.data_ptr(), X.shape[0],
+                                    grad.data_ptr(), loss.data_ptr(), _stream_handle(stream)))
+    return loss, grad
+
+
+def mlp_adam_step(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(lib().emogi_mlp_adam_step(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                    int(t), lr, beta1, beta2, eps, _stream_handle(stream)))
+
+
+def mlp_train(X, y, params, epochs=50, batch=256, lr=1e-3, seed=0):
+    """Trains on the GPU from host arrays; returns (params float32[5638], loss per epoch)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    p = np.ascontiguousarray(params, dtype=np.float32).copy()
+    hist = np.zeros(epochs, dtype=np.float32)
+    cfg = TrainConfig(lr, 0.9, 0.999, 1e-8, batch, epochs, seed)
+    check(lib().emogi_mlp_train(X.ctypes.data, y.ctypes.data, X.shape[0], ctypes.byref(cfg),
+                                p.ctypes.data, hist.ctypes.data))
+    return p, hist
 
 
 _lib = None
@@ -100,6 +192,18 @@ def lib():
             "emogi_last_stats": (i32, [p, ctypes.POINTER(Stats)]),
             "emogi_num_vertices": (u64, [p]),
             "emogi_num_edges": (u64, [p]),
+            "emogi_calibrate_link": (i32, [sz, ctypes.POINTER(LinkProfile)]),
+            "emogi_mlp_forward": (i32, [p, p, u32, p, p]),
+            "emogi_mlp_loss_grad": (i32, [p, p, p, u32, p, p, p]),
+            "emogi_mlp_adam_step": (i32, [p, p, p, p, u32, ctypes.c_float, ctypes.c_float,
+                                          ctypes.c_float, ctypes.c_float, p]),
+            "emogi_mlp_train": (i32, [p, p, u32, ctypes.POINTER(TrainConfig), p, p]),
+            "emogi_bfs_batch": (i32, [p, p, u32, p, p]),
+            "emogi_sssp_batch": (i32, [p, p, u32, p, p]),
+            "emogi_set_batch_params": (i32, [p, ctypes.POINTER(BatchParams)]),
+            "emogi_get_batch_params": (i32, [p, ctypes.POINTER(BatchParams)]),
+            "emogi_autotune_batch": (i32, [p, i32, p, u32, p, p, ctypes.POINTER(BatchParams),
+                                           ctypes.POINTER(BatchTrial), u32]),
             "emogi_strerror": (ctypes.c_char_p, [i32]),
             "emogi_last_error": (ctypes.c_char_p, []),
         }
@@ -142,6 +246,13 @@ class PinnedArray:
             self.free()
         except Exception:
             pass
+
+
+def calibrate_link(nbytes=1 << 30):
+    """Runs emogi_calibrate_link and returns the profile as a dict."""
+    p = LinkProfile()
+    check(lib().emogi_calibrate_link(int(nbytes), ctypes.byref(p)))
+    return p.as_dict()
 
 
 def _addr(a):
@@ -197,9 +308,11 @@ class Graph:
     def set_variant(self, v):
         check(lib().emogi_set_scheduler(self._h, int(v)))
 
-    def set_scheduler(self, mode):
-        modes = {"heuristic": SCHED_HEURISTIC, "learned": SCHED_LEARNED}
-        check(lib().emogi_set_scheduler(self._h, modes[mode] if isinstance(mode, str) else int(mode)))
+    def set_scheduler(self, mode, record=False):
+        """mode: 'heuristic' | 'learned' | 'probe' | variant index; record keeps per-level features."""
+        modes = {"heuristic": SCHED_HEURISTIC, "learned": SCHED_LEARNED, "probe": SCHED_PROBE}
+        m = modes[mode] if isinstance(mode, str) else int(mode)
+        check(lib().emogi_set_scheduler(self._h, m | (SCHED_RECORD if record else 0)))
 
     def set_scheduler_weights(self, params):
         if params is None:
@@ -236,6 +349,59 @@ class Graph:
         out = self._out(out)
         check(lib().emogi_cc(self._h, out.data_ptr(), _stream_handle(stream)))
         return out
+
+    # -- batched multi-source (<= 64 sources share every list read) ----------
+    def _batch_out(self, n, out):
+        import torch
+        if out is None:
+            out = torch.empty(n * max(1, self.num_vertices), dtype=torch.int32, device="cuda")
+        if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous():
+            raise TypeError("output must be a contiguous int32 CUDA/HIP tensor")
+        if out.numel() < n * self.num_vertices:
+            raise ValueError("output tensor too small")
+        return out
+
+    def _srcs(self, srcs):
+        s = np.ascontiguousarray(srcs, dtype=np.uint64)
+        if not 1 <= s.shape[0] <= 64:
+            raise ValueError("1..64 sources")
+        return s
+
+    def bfs_batch(self, srcs, out=None, stream=None):
+        """Levels from each source, source-major [n * V] int32 tensor."""
+        s = self._srcs(srcs)
+        out = self._batch_out(s.shape[0], out)
+        check(lib().emogi_bfs_batch(self._h, s.ctypes.data, s.shape[0], out.data_ptr(),
+                                    _stream_handle(stream)))
+        return out
+
+    def sssp_batch(self, srcs, out=None, stream=None):
+        s = self._srcs(srcs)
+        out = self._batch_out(s.shape[0], out)
+        check(lib().emogi_sssp_batch(self._h, s.ctypes.data, s.shape[0], out.data_ptr(),
+                                     _stream_handle(stream)))
+        return out
+
+    def set_batch_params(self, hub_degree=1024, steps_per_graph=4, blocks_per_cu=8, use_graph=True):
+        p = BatchParams(hub_degree, steps_per_graph, blocks_per_cu, int(use_graph))
+        check(lib().emogi_set_batch_params(self._h, ctypes.byref(p)))
+
+    def get_batch_params(self):
+        p = BatchParams()
+        check(lib().emogi_get_batch_params(self._h, ctypes.byref(p)))
+        return p.as_dict()
+
+    def autotune_batch(self, algo, srcs, out=None, stream=None):
+        """Tries the candidate parameter sets; keeps and returns the fastest plus the table."""
+        s = self._srcs(srcs)
+        out = self._batch_out(s.shape[0], out)
+        best = BatchParams()
+        table = (BatchTrial * 64)()
+        check(lib().emogi_autotune_batch(self._h, {"bfs": 0, "sssp": 1}[algo], s.ctypes.data,
+                                         s.shape[0], out.data_ptr(), _stream_handle(stream),
+                                         ctypes.byref(best), table, 64))
+        trials = [dict(t.params.as_dict(), ms=t.ms) for t in table if t.params.blocks_per_cu]
+        return best.as_dict(), trials
 
     def stats(self):
         s = Stats()

@@ -1,0 +1,178 @@
+"""Trains the per-level variant scheduler and evaluates it on held-out graphs.
+
+1. Harvest: on training graphs shaped like the benchmark configurations
+   (R-MAT scale 16 with 4-byte ids; R-MAT with 8-byte ids; uniform random with
+   4-byte ids; graph seeds 1, 2, 3), run BFS, SSSP and CC in probe mode: every
+   level is run with all six access variants on the same state, and the 16
+   frontier features plus the six kernel times are kept.  The label of a level
+   is its fastest variant.
+2. Train: the 16-64-64-6 network is trained on the GPU by the library's own
+   HIP kernels (emogi_mlp_train: forward, softmax cross-entropy, backward,
+   Adam), from a seeded He-uniform initialisation.
+3. Evaluate: on held-out locality-ordered power-law graphs (seeds 101-103),
+   time each traversal with the fixed aligned-wave variant (the paper's
+   choice), the built-in heuristic, the learned scheduler, and report the
+   per-level best (sum over levels of the fastest variant's probe time).
+
+Writes ``scheduler_weights.json`` next to this file:
+``{"params": [5638 floats], "train": {...}, "eval": {...}}``.
+
+Usage: python -m paper_2006_06890_amd.train_scheduler [--quick]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "scheduler_weights.json")
+
+
+def log(*a):
+    print("[train]", *a, flush=True)
+
+
+def _graph(E, graphgen, spec):
+    kind, size, col_bytes, seed = spec
+    if kind == "rmat":
+        h = graphgen.rmat(size, 16, seed=seed)
+    elif kind == "uniform":
+        h = graphgen.uniform(size, (1 << size) * 32, seed=seed)
+    else:
+        h = graphgen.power_law(size, seed=seed)
+    g = h.to_csr(col_bytes, weights=True)
+    h.free()
+    return g
+
+
+def _sources(g, k, seed):
+    deg = g.degrees()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nz = np.flatnonzero(deg > 0)
+    return [int(x) for x in rng.choice(nz, size=min(k, nz.shape[0]), replace=False)]
+
+
+def _runs(G, g, out, algo, srcs):
+    if algo == "cc":
+        G.cc(out)
+        yield G.stats()
+    else:
+        for s in srcs:
+            getattr(G, algo)(s, out)
+            yield G.stats()
+
+
+def harvest(E, graphgen, specs, torch):
+    X, T = [], []
+    for spec in specs:
+        t0 = time.time()
+        g = _graph(E, graphgen, spec)
+        out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+        with E.Graph(g.row_ptr, g.col, g.weights, placement="host_zero_copy", symmetric=True) as G:
+            G.set_scheduler("probe", record=True)
+            for algo, k in (("bfs", 3), ("sssp", 2), ("cc", 1)):
+                for st in _runs(G, g, out, algo, _sources(g, k, spec[3] + 17)):
+                    for f, p in zip(st["level_features"], st["level_probe_ms"]):
+                        X.append(f)
+                        T.append(p)
+        log(f"harvested {spec}: {len(X)} levels so far ({time.time() - t0:.1f}s)")
+    return np.array(X, dtype=np.float32), np.array(T, dtype=np.float32)
+
+
+def he_uniform(seed):
+    from_shapes = [(64, 16), (64,), (64, 64), (64,), (6, 64), (6,)]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for s in from_shapes:
+        if len(s) == 2:
+            lim = np.sqrt(6.0 / s[1])
+            parts.append(rng.uniform(-lim, lim, size=s).ravel())
+        else:
+            parts.append(np.zeros(s))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def evaluate(E, graphgen, specs, params, torch):
+    rows = []
+    for spec in specs:
+        g = _graph(E, graphgen, spec)
+        out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+        srcs = _sources(g, 2, spec[3] + 5)
+        with E.Graph(g.row_ptr, g.col, g.weights, placement="host_zero_copy", symmetric=True) as G:
+            G.set_scheduler_weights(params)
+            for algo in ("bfs", "sssp", "cc"):
+                res = {}
+                for mode in ("fixed_v3", "heuristic", "learned", "probe"):
+                    if mode == "fixed_v3":
+                        G.set_variant(3)
+                    else:
+                        G.set_scheduler(mode, record=(mode == "learned"))
+                    tot = 0.0
+                    best = 0.0
+                    picks = []
+                    for st in _runs(G, g, out, algo, srcs):
+                        tot += st["total_ms"]
+                        if mode == "probe":
+                            best += float(np.sum(np.min(np.array(st["level_probe_ms"]), axis=1)))
+                        if mode == "learned":
+                            picks += st["level_variant"]
+                    res[mode] = tot if mode != "probe" else best
+                    if mode == "learned":
+                        res["learned_picks"] = np.bincount(picks, minlength=6).tolist()
+                row = {"graph": list(spec), "algo": algo, "ms": {k: round(v, 3) for k, v in res.items()
+                                                                if k != "learned_picks"},
+                       "learned_picks": res["learned_picks"]}
+                rows.append(row)
+                log(f"eval {spec} {algo}: {row['ms']} picks {row['learned_picks']}")
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true", help="small graphs (a smoke run)")
+    ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--eval-vertices", type=int, default=1 << 24)
+    args = ap.parse_args()
+
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+    import graphgen
+    import paper_2006_06890_amd as E
+
+    if args.quick:
+        train_specs = [("rmat", 14, 4, 1), ("rmat", 14, 8, 2), ("uniform", 14, 4, 3)]
+        eval_specs = [("powerlaw", 1 << 16, 4, 101)]
+    else:
+        train_specs = []
+        for seed in (1, 2, 3):
+            train_specs += [("rmat", 16, 4, seed), ("rmat", 21, 8, seed), ("rmat", 22, 4, seed),
+                            ("uniform", 20, 4, seed), ("uniform", 22, 4, seed)]
+        eval_specs = [("powerlaw", args.eval_vertices, 4, s) for s in (101, 102, 103)]
+
+    X, T = harvest(E, graphgen, train_specs, torch)
+    y = np.argmin(T, axis=1).astype(np.int32)
+    log(f"{X.shape[0]} levels; label histogram {np.bincount(y, minlength=6).tolist()}")
+    # replicate small datasets so every epoch has several full minibatches
+    reps = max(1, 2048 // X.shape[0])
+    Xr, yr = np.tile(X, (reps, 1)), np.tile(y, reps)
+    p0 = he_uniform(7)
+    params, hist = E.emogi.mlp_train(Xr, yr, p0, epochs=args.epochs, batch=min(256, Xr.shape[0]),
+                                     lr=1e-3, seed=11)
+    log(f"loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    rows = evaluate(E, graphgen, eval_specs, params, torch)
+    json.dump({
+        "params": [float(x) for x in params],
+        "train": {"specs": train_specs, "levels": int(X.shape[0]),
+                  "label_hist": np.bincount(y, minlength=6).tolist(),
+                  "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+                  "epochs": args.epochs},
+        "eval": rows,
+    }, open(WEIGHTS, "w"))
+    log(f"wrote {WEIGHTS}")
+
+
+if __name__ == "__main__":
+    main()
