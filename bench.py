@@ -44,8 +44,8 @@ def build_graph(args, E, graphgen):
     log(f"[bench] generated {h.name}: V={V} E={M} in {time.time() - t:.1f}s")
     t = time.time()
     rp = np.empty(V + 1, dtype=np.uint64)
-    col = E.PinnedArray(M, np.uint64 if args.col_bytes == 8 else np.uint32)
-    w = E.PinnedArray(M, np.uint32)
+    col = E.PinnedArray(M, np.uint64 if args.col_bytes == 8 else np.uint32, noncoherent=args.noncoherent)
+    w = E.PinnedArray(M, np.uint32, noncoherent=args.noncoherent)
     h.export_into(rp.ctypes.data, col.ptr, args.col_bytes, w.ptr, 3)
     h.free()
     log(f"[bench] exported into pinned memory in {time.time() - t:.1f}s")
@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--request-unit", type=int, default=256)
     ap.add_argument("--no-arms", action="store_true", help="skip the HBM/managed comparison runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-source batched runs")
+    ap.add_argument("--noncoherent", action="store_true", help="pin the edge arrays non-coherent")
+    ap.add_argument("--no-learned", action="store_true", help="skip the scheduler comparison")
     ap.add_argument("--cpu-scale", type=int, default=24)
     ap.add_argument("--calib-bytes", type=int, default=1 << 30)
     ap.add_argument("--calibrate-only", action="store_true",
@@ -282,6 +285,45 @@ def main():
         result["roofline"]["traffic_fetch_write"] = round(ct["fetch_bytes_per_dispatch_scaled"]
                                                           + ct["write_bytes_per_dispatch"])
         result["roofline"]["traffic_source"] = "profiles/counters_kron27_u64.json"
+
+    # --- the two systems patterns, each against the plain method on this GPU ---
+    plain_bfs_ms = per["bfs"]["ms"] / len(steps)
+    plain_sssp_ms = per["sssp"]["ms"] / len(steps)
+    if not args.no_batch:
+        srcs64 = graphgen.degree_spread_sources(rp, 64, seed=4)
+        out64 = torch.empty(len(srcs64) * V, dtype=torch.int32, device="cuda")
+        G.bfs_batch(srcs64, out64)
+        sb = G.stats()
+        G.sssp_batch(srcs64, out64)
+        ss = G.stats()
+        del out64
+        result["batched"] = {
+            "sources": len(srcs64), "source_degrees": "log-spaced 1..max (seed 4)",
+            "bfs_ms": round(sb["total_ms"], 1), "sssp_ms": round(ss["total_ms"], 1),
+            "plain_bfs_ms_x_sources": round(plain_bfs_ms * len(srcs64), 1),
+            "plain_sssp_ms_x_sources": round(plain_sssp_ms * len(srcs64), 1),
+            "bfs_speedup_vs_plain": round(plain_bfs_ms * len(srcs64) / sb["total_ms"], 2),
+            "sssp_speedup_vs_plain": round(plain_sssp_ms * len(srcs64) / ss["total_ms"], 2),
+            "params": G.get_batch_params(),
+        }
+        log(f"[bench] batched: {result['batched']}")
+    weights = os.path.join(ROOT, "paper_2006_06890_amd", "scheduler_weights.json")
+    if not args.no_learned:
+        sched = {}
+        modes = [("fixed_v3", 3), ("heuristic", "heuristic")]
+        if os.path.exists(weights):
+            G.set_scheduler_weights(json.load(open(weights))["params"])
+            modes.append(("learned", "learned"))
+        for name, mode in modes:
+            if isinstance(mode, int):
+                G.set_variant(mode)
+            else:
+                G.set_scheduler(mode)
+            r = run_step(G, sources[0], out, torch)
+            sched[name] = {a: round(r[a]["total_ms"], 1) for a in r}
+            sched[name]["step_ms"] = round(sum(r[a]["total_ms"] for a in r), 1)
+        result["schedulers"] = sched
+        log(f"[bench] schedulers (one step, source {sources[0]}): {sched}")
 
     G.close()
     if not args.no_arms:

@@ -160,6 +160,27 @@ emogi_status_t emogi_graph_destroy(emogi_graph_t g);
  * host link at its copy rate when read at random. */
 emogi_status_t emogi_set_request_unit(emogi_graph_t g, uint32_t bytes);
 emogi_status_t emogi_set_scheduler(emogi_graph_t g, int mode);
+/* SSSP distance band (near-far worklist): an improved vertex whose new
+ * distance is below the current split joins the next frontier, otherwise it
+ * waits in a far pile; when the near frontier empties the split moves to the
+ * smallest waiting distance + delta.  0 disables the bands (every improved
+ * vertex re-enters at once).  Default 8.  Results are identical for any
+ * value; only the amount of re-expansion changes. */
+emogi_status_t emogi_set_sssp_delta(emogi_graph_t g, uint32_t delta);
+/* CC algorithm (both give every vertex the smallest id of its component):
+ * EMOGI_CC_LABEL_PROPAGATION: all vertices start active and push their label
+ *   over every list until nothing changes (the paper's workload, Sec. 5.4);
+ * EMOGI_CC_SAMPLED_UNION_FIND (default): hook each vertex to its first two
+ *   neighbours, compress, then read whole lists only for vertices outside
+ *   the largest tree found (Afforest-style; far fewer list bytes). */
+/* Frontier order: 0 appends pushes through per-wave LDS segments (order
+ * unspecified); 1 (default) collects the next frontier as a bitmap and lists
+ * it in ascending vertex id, so each level reads neighbour lists in
+ * edge-array order.  Results are identical either way. */
+emogi_status_t emogi_set_frontier_order(emogi_graph_t g, int ordered);
+#define EMOGI_CC_LABEL_PROPAGATION 0
+#define EMOGI_CC_SAMPLED_UNION_FIND 1
+emogi_status_t emogi_set_cc_algorithm(emogi_graph_t g, int algorithm);
 /* Loads the 5638 fp32 scheduler parameters (order W1,b1,W2,b2,W3,b3, row-major)
  * from host memory; NULL clears them (learned mode then uses the heuristic). */
 emogi_status_t emogi_set_scheduler_weights(emogi_graph_t g, const float *params, size_t count);

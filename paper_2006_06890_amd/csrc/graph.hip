@@ -130,7 +130,9 @@ static void release(emogi_graph_s *g) {
     if (p.host_counters) (void)hipHostFree(p.host_counters);
     if (p.features) (void)hipFree(p.features);
     if (p.degree_hist) (void)hipFree(p.degree_hist);
-    for (void *x : {(void *)p.snap_state, (void *)p.snap_stamp, (void *)p.snap_bitmap})
+    for (void *x : {(void *)p.snap_state, (void *)p.snap_stamp, (void *)p.snap_bitmap, (void *)p.far[0],
+                    (void *)p.far[1], (void *)p.farbits, (void *)p.snap_farbits, (void *)p.cc_probe,
+                    (void *)p.nextbits})
         if (x) (void)hipFree(x);
     if (g->mlp_params) (void)hipFree(g->mlp_params);
     BatchPool &b = g->batch;
@@ -348,6 +350,33 @@ emogi_status_t emogi_graph_destroy(emogi_graph_t g) {
     if (!g) return EMOGI_E_INVALID;
     (void)hipDeviceSynchronize();
     release(g);
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_set_frontier_order(emogi_graph_t g, int ordered) {
+    if (!g) {
+        set_error("null graph");
+        return EMOGI_E_INVALID;
+    }
+    g->ordered_frontier = ordered != 0;
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_set_cc_algorithm(emogi_graph_t g, int algorithm) {
+    if (!g || (algorithm != EMOGI_CC_LABEL_PROPAGATION && algorithm != EMOGI_CC_SAMPLED_UNION_FIND)) {
+        set_error("unknown CC algorithm %d", algorithm);
+        return EMOGI_E_INVALID;
+    }
+    g->cc_sampled = algorithm == EMOGI_CC_SAMPLED_UNION_FIND;
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_set_sssp_delta(emogi_graph_t g, uint32_t delta) {
+    if (!g) {
+        set_error("null graph");
+        return EMOGI_E_INVALID;
+    }
+    g->sssp_delta = delta;
     return EMOGI_OK;
 }
 

@@ -31,6 +31,8 @@ enum Counter : int {
     C_REQBYTES = 2,  // request-granular link bytes of those lists
     C_OVERFLOW = 3,  // SSSP: some relaxation exceeded 0xFFFFFFFE
     C_VERTS = 4,     // expanded vertices
+    C_FAR = 5,       // SSSP: entries appended to the far pile
+    C_FARMIN = 6,    // SSSP: smallest live distance in the far pile
     C_COUNT = 8
 };
 
@@ -47,6 +49,11 @@ struct Pool {
     uint32_t *snap_state = nullptr;           // probe mode: saved state of a level
     uint32_t *snap_stamp = nullptr;
     uint32_t *snap_bitmap = nullptr;
+    uint32_t *far[2] = {nullptr, nullptr};    // SSSP near-far: far piles (V entries each)
+    uint32_t *farbits = nullptr;              // SSSP near-far: in-far-pile bit per vertex
+    uint32_t *snap_farbits = nullptr;
+    uint32_t *cc_probe = nullptr;             // CC: roots of probed vertices
+    uint32_t *nextbits = nullptr;             // ordered frontier bitmap
     size_t chunk_cap = 0;
 };
 
@@ -79,6 +86,9 @@ struct emogi_graph_s {
     enum Kind { NONE, DEVICE, PINNED, MANAGED, BORROWED } col_kind = NONE, w_kind = NONE;
 
     uint32_t request_unit = 256;
+    uint32_t sssp_delta = 8;       // near-far band width; 0 = plain label correcting
+    bool cc_sampled = true;        // CC by sampled union-find (else min-label propagation)
+    bool ordered_frontier = true;  // list each next frontier in ascending id order
     int sched_mode = EMOGI_SCHED_HEURISTIC;
     bool record_features = false;  // store per-level frontier features in the stats
     float *mlp_params = nullptr;   // device, 5638 floats, or null

@@ -29,7 +29,7 @@
 
 namespace emogi {
 
-enum Algo { A_BFS = 0, A_SSSP = 1, A_CC = 2 };
+enum Algo { A_BFS = 0, A_SSSP = 1, A_CC = 2, A_LINK = 3 };  // A_LINK: CC union-find hooking pass
 
 constexpr int kUnroll = 4;        // loads in flight per lane in the wave variants
 constexpr int kChunksPerWave = 8; // V5: consecutive aligned chunks per wave visit
@@ -59,45 +59,101 @@ struct OpArgs {
     uint32_t *stamp;    // SSSP/CC: last round in which v was pushed
     uint32_t tag;       // BFS: level of the next frontier; SSSP/CC: round number
     uint32_t V;         // neighbour ids at or above V are ignored (malformed input)
+    uint32_t split;     // SSSP near-far: improvements at or above it go to the far pile
+    uint32_t *far;      // SSSP: far pile (append at ctr[C_FAR])
+    uint32_t *farbits;  // SSSP: one bit per vertex already in the far pile
+    uint32_t *nextbits; // ordered frontier: next frontier as a bitmap (null: LDS-staged queue)
     unsigned long long *ctr;
 };
 
 template <int A>
 __device__ __forceinline__ uint32_t source_value(const OpArgs &a, uint32_t u) {
     if (A == A_BFS) return 0u;
+    if (A == A_LINK) return u;
     return a.state[u];
 }
 
-// Returns true when v joins the next frontier.
+__device__ __forceinline__ uint32_t load_parent(const uint32_t *parent, uint32_t x) {
+    return __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Union of the trees of a and b in a parent forest where every parent id is
+// at most its child's id: a root is only ever hooked below a smaller id, so
+// the root of each finished tree is the smallest id of its component.  The
+// larger of the two current roots strictly decreases every round, so the
+// loop ends (the hooking step of Afforest, Sutton et al. 2018).
+__device__ __forceinline__ void uf_link(uint32_t *parent, uint32_t a, uint32_t b) {
+    uint32_t p1 = load_parent(parent, a), p2 = load_parent(parent, b);
+    while (p1 != p2) {
+        const uint32_t high = p1 > p2 ? p1 : p2, low = p1 > p2 ? p2 : p1;
+        const uint32_t ph = load_parent(parent, high);
+        if (ph == low) break;
+        if (ph == high && atomicCAS(&parent[high], high, low) == high) break;
+        p1 = load_parent(parent, load_parent(parent, high));
+        p2 = load_parent(parent, low);
+    }
+}
+
+// Returns 1 when v joins the next frontier, 2 when it joins the SSSP far pile, else 0.
 template <int A>
-__device__ __forceinline__ bool visit(const OpArgs &a, uint32_t uval, uint32_t v, uint32_t w) {
-    if (v >= a.V) return false;
+__device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v, uint32_t w) {
+    if (v >= a.V) return 0;
     if (A == A_BFS) {
         // BFS: an unvisited neighbour is visited at the next level.
         uint32_t word = v >> 5, bit = 1u << (v & 31u);
-        if (a.bitmap[word] & bit) return false;
+        if (a.bitmap[word] & bit) return 0;
         uint32_t old = atomicOr(&a.bitmap[word], bit);
-        if (old & bit) return false;
+        if (old & bit) return 0;
         a.state[v] = a.tag;
-        return true;
+        return 1;
     } else if (A == A_SSSP) {
         // SSSP: relax the edge; an improved vertex is re-activated once per round.
         uint64_t nd = uint64_t(uval) + w;
         if (nd > 0xFFFFFFFEull) {
             atomicOr(&a.bitmap[v >> 5], 1u << (v & 31u));
             atomicOr(&a.ctr[C_OVERFLOW], 1ull);
-            return false;
+            return 0;
         }
-        if (a.state[v] <= uint32_t(nd)) return false;
+        if (a.state[v] <= uint32_t(nd)) return 0;
         uint32_t old = atomicMin(&a.state[v], uint32_t(nd));
-        if (old <= uint32_t(nd)) return false;
-        return atomicExch(&a.stamp[v], a.tag) != a.tag;
+        if (old <= uint32_t(nd)) return 0;
+        if (uint32_t(nd) >= a.split) {
+            // beyond the current distance band: park it in the far pile once
+            const uint32_t bit = 1u << (v & 31u);
+            return (atomicOr(&a.farbits[v >> 5], bit) & bit) ? 0 : 2;
+        }
+        return atomicExch(&a.stamp[v], a.tag) != a.tag ? 1 : 0;
+    } else if (A == A_LINK) {
+        uf_link(a.state, uval, v);
+        return 0;
     } else {
         // CC: push the smaller label; a lowered vertex is re-activated once per round.
-        if (a.state[v] <= uval) return false;
+        if (a.state[v] <= uval) return 0;
         uint32_t old = atomicMin(&a.state[v], uval);
-        if (old <= uval) return false;
-        return atomicExch(&a.stamp[v], a.tag) != a.tag;
+        if (old <= uval) return 0;
+        return atomicExch(&a.stamp[v], a.tag) != a.tag ? 1 : 0;
+    }
+}
+
+// Hands a visit result to the next-frontier staging (1) or the far pile (2).
+// Uniform: every lane of the wave calls it.
+template <int A>
+__device__ __forceinline__ void emit(Stage &st, int r, uint32_t v, uint32_t *next, const OpArgs &a,
+                                     int lane) {
+    if (a.nextbits) {
+        // ordered frontier: mark; a compaction pass later lists the marks in id order
+        if (r == 1) atomicOr(&a.nextbits[v >> 5], 1u << (v & 31u));
+    } else {
+        stage(st, r == 1, v, next, &a.ctr[C_NEXT], lane);
+    }
+    if (A == A_SSSP) {
+        const uint64_t m = __ballot(r == 2);
+        if (m) {
+            uint32_t base = 0;
+            if (lane == 0) base = uint32_t(atomicAdd(&a.ctr[C_FAR], (unsigned long long)__popcll(m)));
+            base = __shfl(base, 0);
+            if (r == 2) a.far[base + rank_below(m)] = v;
+        }
     }
 }
 
@@ -162,8 +218,8 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s, OpArgs a) {
             }
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
-                const bool p = ok[k] && visit<A>(a, uval, v[k], w[k]);
-                stage(st, p, v[k], s.next, &a.ctr[C_NEXT], lane);
+                const int r = ok[k] ? visit<A>(a, uval, v[k], w[k]) : 0;
+                emit<A>(st, r, v[k], s.next, a, lane);
             }
         }
     }
@@ -207,8 +263,8 @@ __global__ __launch_bounds__(kBlock) void k_block(ScanArgs s, OpArgs a) {
             }
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                const bool p = ok[k] && visit<A>(a, uval, v[k], w[k]);
-                stage(st, p, v[k], s.next, &a.ctr[C_NEXT], lane);
+                const int r = ok[k] ? visit<A>(a, uval, v[k], w[k]) : 0;
+                emit<A>(st, r, v[k], s.next, a, lane);
             }
         }
     }
@@ -257,8 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_group(ScanArgs s, OpArgs a) {
                 v = load_col(col, j);
                 if (A == A_SSSP) w = s.w[j];
             }
-            const bool p = ok && visit<A>(a, uval, v, w);
-            stage(st, p, v, s.next, &a.ctr[C_NEXT], lane);
+            const int r = ok ? visit<A>(a, uval, v, w) : 0;
+            emit<A>(st, r, v, s.next, a, lane);
         }
     }
     finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts);
@@ -342,8 +398,8 @@ __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s, OpArgs a) {
             }
 #pragma unroll
             for (int i = 0; i < kUnroll; ++i) {
-                const bool p = ok[i] && visit<A>(a, uv[i], v[i], w[i]);
-                stage(st, p, v[i], s.next, &a.ctr[C_NEXT], lane);
+                const int r = ok[i] ? visit<A>(a, uv[i], v[i], w[i]) : 0;
+                emit<A>(st, r, v[i], s.next, a, lane);
             }
         }
     }
@@ -448,6 +504,170 @@ __global__ void k_seed_source(uint32_t *state, uint32_t *bitmap, uint32_t *queue
     }
 }
 
+// ---------------------------------------------------------------------------
+// SSSP near-far: when the near frontier runs dry, the far pile is re-cut at
+// a new split = (smallest live far distance) + delta.  Entries below the old
+// split are stale (those vertices were settled and expanded in an earlier
+// band), entries below the new split become the next near frontier, the rest
+// stay in the (compacted) far pile.  Distances are unchanged: only the order
+// in which vertices are expanded differs, so the result stays exact.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_far_min(const uint32_t *far, uint64_t n, const uint32_t *dist,
+                                                     uint32_t split, unsigned long long *ctr) {
+    uint32_t m = 0xFFFFFFFFu;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+        const uint32_t d = dist[far[i]];
+        if (d >= split && d < m) m = d;
+    }
+    for (int o = 32; o > 0; o >>= 1) m = min(m, uint32_t(__shfl_xor(m, o)));
+    if (lane_id() == 0 && m != 0xFFFFFFFFu) atomicMin(&ctr[C_FARMIN], (unsigned long long)m);
+}
+
+__device__ __forceinline__ void push_ballot(bool p, uint32_t v, uint32_t *dst, unsigned long long *count,
+                                            int lane) {
+    const uint64_t m = __ballot(p);
+    if (!m) return;
+    uint32_t base = 0;
+    if (lane == 0) base = uint32_t(atomicAdd(count, (unsigned long long)__popcll(m)));
+    base = __shfl(base, 0);
+    if (p) dst[base + rank_below(m)] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_far_split(const uint32_t *far, uint64_t n, const uint32_t *dist,
+                                                       uint32_t old_split, uint32_t new_split,
+                                                       uint32_t *farbits, uint32_t *nearq,
+                                                       uint32_t *far_out, unsigned long long *ctr) {
+    const int lane = lane_id();
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    // whole waves step together so the ballots see every lane
+    for (uint64_t i0 = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); i0 < n; i0 += stride) {
+        const uint64_t i = i0 + lane;
+        bool to_near = false, keep = false;
+        uint32_t v = 0;
+        if (i < n) {
+            v = far[i];
+            const uint32_t d = dist[v];
+            if (d < new_split) {
+                atomicAnd(&farbits[v >> 5], ~(1u << (v & 31u)));
+                to_near = d >= old_split;
+            } else {
+                keep = true;
+            }
+        }
+        push_ballot(to_near, v, nearq, &ctr[C_NEXT], lane);
+        push_ballot(keep, v, far_out, &ctr[C_FAR], lane);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ordered frontier: the next frontier is collected as a bitmap during the
+// scan and listed here in ascending id order (so the next level reads
+// neighbour lists in edge-array order), clearing the bitmap as it goes.
+// ---------------------------------------------------------------------------
+constexpr int kBitsPerThread = 16;                     // words per thread
+constexpr int kBitsTile = kBlock * kBitsPerThread;     // words per block
+
+__global__ __launch_bounds__(kBlock) void k_bits_count(const uint32_t *bits, uint64_t words,
+                                                        uint64_t *block_sums) {
+    uint64_t c = 0;
+    const uint64_t base = uint64_t(blockIdx.x) * kBitsTile + uint64_t(threadIdx.x) * kBitsPerThread;
+    for (int i = 0; i < kBitsPerThread; ++i)
+        if (base + i < words) c += __popc(bits[base + i]);
+    uint64_t tot;
+    (void)block_exclusive_scan(c, &tot);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t words,
+                                                        const uint64_t *block_offsets, uint32_t nb,
+                                                        uint32_t *queue, unsigned long long *ctr) {
+    const uint64_t base = uint64_t(blockIdx.x) * kBitsTile + uint64_t(threadIdx.x) * kBitsPerThread;
+    uint64_t c = 0;
+    for (int i = 0; i < kBitsPerThread; ++i)
+        if (base + i < words) c += __popc(bits[base + i]);
+    uint64_t tot;
+    uint64_t pos = block_offsets[blockIdx.x] + block_exclusive_scan(c, &tot);
+    for (int i = 0; i < kBitsPerThread; ++i) {
+        if (base + i >= words) break;
+        uint32_t w = bits[base + i];
+        if (!w) continue;
+        bits[base + i] = 0u;
+        while (w) {
+            const int b = __ffs(w) - 1;
+            w &= w - 1;
+            queue[pos++] = uint32_t((base + i) * 32 + b);
+        }
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) ctr[C_NEXT] = block_offsets[blockIdx.x] + tot;
+}
+
+// ---------------------------------------------------------------------------
+// CC by sampled union-find (the labels equal min-label propagation's: every
+// tree's root is its component's smallest id).
+//   1. hook every vertex to its first kCcSample neighbours (reads a prefix
+//      of each list: one small request per vertex);
+//   2. compress; the most frequent root among sampled vertices is taken as
+//      the large component C;
+//   3. scan the whole lists of the vertices outside C only: an edge with one
+//      end in C is also in the other end's list, so no edge that could join
+//      two trees is skipped (symmetric graphs only);
+//   4. compress again: label = root.
+// ---------------------------------------------------------------------------
+constexpr int kCcSample = 2;
+constexpr int kCcProbe = 1024;
+
+template <class ColT>
+__global__ __launch_bounds__(kBlock) void k_cc_sample(const uint64_t *row_ptr, const ColT *col, uint64_t V,
+                                                      uint32_t *parent, unsigned long long *ctr) {
+    uint64_t edges = 0;
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
+         v += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t b = row_ptr[v], e = row_ptr[v + 1];
+        const uint64_t n = e - b < kCcSample ? e - b : kCcSample;
+        ColT nb[kCcSample];
+        for (uint64_t r = 0; r < n; ++r) nb[r] = col[b + r];
+        for (uint64_t r = 0; r < n; ++r)
+            if (uint64_t(nb[r]) < V) uf_link(parent, uint32_t(v), uint32_t(nb[r]));
+        edges += n;
+    }
+    edges = wave_sum64(edges);
+    if (lane_id() == 0 && edges) atomicAdd(&ctr[C_EDGES], (unsigned long long)edges);
+}
+
+__global__ void k_compress(uint32_t *parent, uint64_t V) {
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
+         v += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t r = parent[v];
+        while (parent[r] != r) r = parent[r];
+        parent[v] = r;
+    }
+}
+
+// Roots of kCcProbe pseudo-randomly chosen vertices (SplitMix64 of the index).
+__global__ void k_cc_probe(const uint32_t *parent, uint64_t V, uint32_t *roots) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kCcProbe) return;
+    uint64_t z = (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    roots[i] = parent[z % V];
+}
+
+// Vertices with edges whose root is not `big`, in id order per wave.
+__global__ __launch_bounds__(kBlock) void k_cc_outside(const uint32_t *parent, const uint64_t *row_ptr,
+                                                        uint64_t V, uint32_t big, uint32_t *queue,
+                                                        unsigned long long *ctr) {
+    const int lane = lane_id();
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i0 = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); i0 < V; i0 += stride) {
+        const uint64_t v = i0 + lane;
+        const bool p = v < V && parent[v] != big && row_ptr[v + 1] > row_ptr[v];
+        push_ballot(p, uint32_t(v), queue, &ctr[C_NEXT], lane);
+    }
+}
+
 // SSSP: a vertex that saw an overflowing relaxation and never got a finite
 // distance is reachable only by paths longer than 0xFFFFFFFE.
 __global__ void k_overflow_check(const uint32_t *dist, const uint32_t *marks, uint64_t V,
@@ -488,6 +708,17 @@ static emogi_status_t ensure_pool(emogi_graph_s *g, int algo) {
     if (algo != A_BFS &&
         (st = dalloc(reinterpret_cast<void **>(&p.stamp), V * sizeof(uint32_t))) != EMOGI_OK)
         return st;
+    if (algo == A_CC &&
+        (st = dalloc(reinterpret_cast<void **>(&p.cc_probe), kCcProbe * sizeof(uint32_t))) != EMOGI_OK)
+        return st;
+    if (algo == A_SSSP && g->sssp_delta > 0) {
+        for (int i = 0; i < 2; ++i)
+            if ((st = dalloc(reinterpret_cast<void **>(&p.far[i]), V * sizeof(uint32_t))) != EMOGI_OK)
+                return st;
+        if ((st = dalloc(reinterpret_cast<void **>(&p.farbits), ((V + 31) / 32) * sizeof(uint32_t))) !=
+            EMOGI_OK)
+            return st;
+    }
     if ((st = dalloc(reinterpret_cast<void **>(&p.counters), C_COUNT * sizeof(unsigned long long))) != EMOGI_OK)
         return st;
     if (!p.host_counters) {
@@ -581,6 +812,15 @@ static emogi_status_t snapshot(emogi_graph_s *g, int algo, uint32_t *out, hipStr
     EMOGI_HIP_TRY(cp(out, p.snap_state, V * 4), EMOGI_E_HIP);
     if (algo != A_CC) EMOGI_HIP_TRY(cp(p.bitmap, p.snap_bitmap, words * 4), EMOGI_E_HIP);
     if (algo != A_BFS) EMOGI_HIP_TRY(cp(p.stamp, p.snap_stamp, V * 4), EMOGI_E_HIP);
+    if (algo == A_SSSP && p.farbits) {
+        if (!p.snap_farbits && hipMalloc(&p.snap_farbits, words * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            p.snap_farbits = nullptr;
+            set_error("probe snapshot allocation failed");
+            return EMOGI_E_OOM_DEVICE;
+        }
+        EMOGI_HIP_TRY(cp(p.farbits, p.snap_farbits, words * 4), EMOGI_E_HIP);
+    }
     return EMOGI_OK;
 }
 
@@ -623,8 +863,52 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     // ---- initial active set (Algorithm 1, set_initial_active_vertex) ----
     uint64_t n;
     bool identity = false;
+    int kalgo = algo;  // the operation the scan kernels run (A_LINK for sampled CC)
     if (V > 0) {
-        if (algo == A_CC) {
+        if (algo == A_CC && g->cc_sampled) {
+            // sampled union-find: hook, compress, find the large tree, then one
+            // full pass over the lists of the vertices outside it
+            hipLaunchKernelGGL(k_iota, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
+            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
+                          EMOGI_E_HIP);
+            if (g->col_bytes == 8)
+                hipLaunchKernelGGL(k_cc_sample<uint64_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, g->row_ptr,
+                                   static_cast<const uint64_t *>(g->col), V, out, p.counters);
+            else
+                hipLaunchKernelGGL(k_cc_sample<uint32_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, g->row_ptr,
+                                   static_cast<const uint32_t *>(g->col), V, out, p.counters);
+            hipLaunchKernelGGL(k_compress, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
+            hipLaunchKernelGGL(k_cc_probe, dim3((kCcProbe + 255) / 256), dim3(256), 0, stream, out, V,
+                               p.cc_probe);
+            std::vector<uint32_t> roots(kCcProbe);
+            EMOGI_HIP_TRY(hipMemcpyAsync(roots.data(), p.cc_probe, kCcProbe * sizeof(uint32_t),
+                                         hipMemcpyDeviceToHost, stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+            S.edges_scanned += p.host_counters[C_EDGES];
+            std::sort(roots.begin(), roots.end());
+            uint32_t big = roots[0], best = 0;
+            for (size_t i = 0, j; i < roots.size(); i = j) {
+                for (j = i; j < roots.size() && roots[j] == roots[i]; ++j) {}
+                if (j - i > best) {
+                    best = uint32_t(j - i);
+                    big = roots[i];
+                }
+            }
+            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
+                          EMOGI_E_HIP);
+            hipLaunchKernelGGL(k_cc_outside, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, g->row_ptr, V, big,
+                               p.queue[0], p.counters);
+            EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+            n = p.host_counters[C_NEXT];
+            kalgo = A_LINK;
+        } else if (algo == A_CC) {
             hipLaunchKernelGGL(k_iota, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
             EMOGI_HIP_TRY(hipMemsetAsync(p.stamp, 0, V * sizeof(uint32_t), stream), EMOGI_E_HIP);
             n = V;
@@ -650,7 +934,56 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     int cur = 0;
     uint32_t iter = 0;
     bool overflow_seen = false;
-    while (n > 0) {
+    // SSSP near-far bands (0 = plain label correcting: every improvement re-enters at once)
+    const bool ordered = g->ordered_frontier && kalgo != A_LINK && V > 0;
+    if (ordered) {
+        if ((st = ensure_scan(g, V)) != EMOGI_OK) return st;
+        if (!p.nextbits && hipMalloc(&p.nextbits, ((V + 31) / 32) * sizeof(uint32_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            p.nextbits = nullptr;
+            set_error("hipMalloc of the ordered-frontier bitmap failed");
+            return EMOGI_E_OOM_DEVICE;
+        }
+        EMOGI_HIP_TRY(hipMemsetAsync(p.nextbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
+    }
+    const bool nearfar = algo == A_SSSP && g->sssp_delta > 0 && V > 0;
+    const uint32_t delta = g->sssp_delta;
+    uint32_t split = nearfar ? delta : 0xFFFFFFFFu;
+    uint64_t far_n = 0;
+    int fcur = 0;
+    if (nearfar)
+        EMOGI_HIP_TRY(hipMemsetAsync(p.farbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
+    while (n > 0 || far_n > 0) {
+        if (n == 0) {
+            // near frontier exhausted: re-cut the far pile at (live minimum + delta)
+            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipMemsetAsync(&p.counters[C_FARMIN], 0xFF, sizeof(unsigned long long), stream),
+                          EMOGI_E_HIP);
+            hipLaunchKernelGGL(k_far_min, dim3(fill_grid(far_n)), dim3(kBlock), 0, stream, p.far[fcur], far_n,
+                               out, split, p.counters);
+            EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+            const unsigned long long m = p.host_counters[C_FARMIN];
+            const uint64_t ns64 = m == ~0ull ? uint64_t(split) : std::min<uint64_t>(m + delta, 0xFFFFFFFFull);
+            const uint32_t new_split = uint32_t(std::max<uint64_t>(ns64, split));
+            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
+                          EMOGI_E_HIP);
+            hipLaunchKernelGGL(k_far_split, dim3(fill_grid(far_n)), dim3(kBlock), 0, stream, p.far[fcur], far_n,
+                               out, split, new_split, p.farbits, p.queue[cur], p.far[fcur ^ 1], p.counters);
+            EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+            n = p.host_counters[C_NEXT];
+            far_n = p.host_counters[C_FAR];
+            fcur ^= 1;
+            split = new_split;
+            continue;
+        }
         if (iter >= cap) {
             (void)hipStreamSynchronize(stream);
             set_error("iteration cap %llu reached", (unsigned long long)cap);
@@ -678,6 +1011,10 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             a.tag = iter + 1;  // BFS: level of the next frontier; SSSP/CC: round
             a.V = uint32_t(V);
             a.ctr = p.counters;
+            a.split = split;
+            a.far = nearfar ? p.far[fcur] + far_n : nullptr;
+            a.farbits = p.farbits;
+            a.nextbits = ordered ? p.nextbits : nullptr;
             EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
                           EMOGI_E_HIP);
             if (v == EMOGI_V5_BALANCED) {
@@ -691,17 +1028,29 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 s.chunk_scan = p.chunk_scan;
             }
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
-            const int key = algo * 2 + (g->col_bytes == 8 ? 1 : 0);
+            const int key = kalgo * 2 + (g->col_bytes == 8 ? 1 : 0);
             switch (key) {
             case 0: launch_variant<uint32_t, A_BFS>(v, s, a, stream); break;
             case 1: launch_variant<uint64_t, A_BFS>(v, s, a, stream); break;
             case 2: launch_variant<uint32_t, A_SSSP>(v, s, a, stream); break;
             case 3: launch_variant<uint64_t, A_SSSP>(v, s, a, stream); break;
             case 4: launch_variant<uint32_t, A_CC>(v, s, a, stream); break;
-            default: launch_variant<uint64_t, A_CC>(v, s, a, stream); break;
+            case 5: launch_variant<uint64_t, A_CC>(v, s, a, stream); break;
+            case 6: launch_variant<uint32_t, A_LINK>(v, s, a, stream); break;
+            default: launch_variant<uint64_t, A_LINK>(v, s, a, stream); break;
             }
             EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
+            if (ordered) {
+                const uint64_t words = (V + 31) / 32;
+                const unsigned nbw = unsigned((words + kBitsTile - 1) / kBitsTile);
+                hipLaunchKernelGGL(k_bits_count, dim3(nbw), dim3(kBlock), 0, stream, p.nextbits, words,
+                                   p.block_sums);
+                hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nbw);
+                hipLaunchKernelGGL(k_bits_write, dim3(nbw), dim3(kBlock), 0, stream, p.nextbits, words,
+                                   p.block_sums, nbw, s.next, p.counters);
+                EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+            }
             EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
                                          hipMemcpyDeviceToHost, stream),
                           EMOGI_E_HIP);
@@ -751,6 +1100,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         S.vertices_expanded += hc[C_VERTS];
         if (hc[C_OVERFLOW]) overflow_seen = true;
         n = hc[C_NEXT];
+        far_n += hc[C_FAR];
         if (identity) {
             identity = false;
             cur = 0;
@@ -759,6 +1109,8 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         }
         ++iter;
     }
+    if (kalgo == A_LINK)
+        hipLaunchKernelGGL(k_compress, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
     S.iterations = iter;
     S.useful_link_bytes = S.edges_scanned * (g->col_bytes + (algo == A_SSSP ? 4u : 0u));
     if (overflow_seen) {

@@ -185,6 +185,9 @@ def lib():
             "emogi_graph_destroy": (i32, [p]),
             "emogi_set_request_unit": (i32, [p, u32]),
             "emogi_set_scheduler": (i32, [p, i32]),
+            "emogi_set_sssp_delta": (i32, [p, u32]),
+            "emogi_set_cc_algorithm": (i32, [p, i32]),
+            "emogi_set_frontier_order": (i32, [p, i32]),
             "emogi_set_scheduler_weights": (i32, [p, p, sz]),
             "emogi_bfs": (i32, [p, u64, p, p]),
             "emogi_sssp": (i32, [p, u64, p, p]),
@@ -320,6 +323,19 @@ class Graph:
             return
         p = np.ascontiguousarray(params, dtype=np.float32)
         check(lib().emogi_set_scheduler_weights(self._h, p.ctypes.data, p.shape[0]))
+
+    def set_frontier_order(self, ordered):
+        """True: list each next frontier in ascending vertex id (bitmap compaction)."""
+        check(lib().emogi_set_frontier_order(self._h, int(bool(ordered))))
+
+    def set_cc_algorithm(self, name):
+        """'label_propagation' or 'sampled_union_find' (default)."""
+        check(lib().emogi_set_cc_algorithm(
+            self._h, {"label_propagation": 0, "sampled_union_find": 1}[name]))
+
+    def set_sssp_delta(self, delta):
+        """SSSP near-far band width (0 = plain label correcting)."""
+        check(lib().emogi_set_sssp_delta(self._h, int(delta)))
 
     def set_request_unit(self, nbytes):
         check(lib().emogi_set_request_unit(self._h, int(nbytes)))

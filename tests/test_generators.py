@@ -89,3 +89,22 @@ def test_sources():
     assert len(set(t)) == len(t) and len(t) >= 32
     degs = g.degrees()[t]
     assert degs.min() >= 1 and degs.max() == g.degrees().max()
+
+
+def test_power_law_locality_order():
+    h = graphgen.chung_lu(50000, 50000 * 18, gamma=2.1, seed=3, permute=False)
+    before = np.sort(np.diff(h.to_csr(4).row_ptr))
+    new_id = h.locality_order(run=1024, seed=3)
+    g = h.to_csr(4)
+    assert np.array_equal(np.sort(new_id), np.arange(50000, dtype=np.uint64))  # a bijection
+    assert np.array_equal(np.sort(g.degrees()), before)                        # same degree multiset
+    assert oracle.validate_csr(g.row_ptr, g.col, simple=True, symmetric=True) == 0
+    # ids inside a run of 1024 keep their first-visit order: neighbours are close in id
+    src = np.repeat(np.arange(g.num_vertices), g.degrees().astype(np.int64))
+    near = np.mean(np.abs(src.astype(np.int64) - g.col.astype(np.int64)) < 1024)
+    rnd = graphgen.chung_lu(50000, 50000 * 18, gamma=2.1, seed=3, permute=True).to_csr(4)
+    src_r = np.repeat(np.arange(rnd.num_vertices), rnd.degrees().astype(np.int64))
+    near_r = np.mean(np.abs(src_r.astype(np.int64) - rnd.col.astype(np.int64)) < 1024)
+    assert near > 2 * near_r, (near, near_r)
+    p = graphgen.power_law(40000, mean_degree=36, seed=101)
+    assert 30 < p.num_edges / p.num_vertices < 42

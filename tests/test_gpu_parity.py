@@ -151,6 +151,79 @@ def test_request_unit_sweep(gpu_device):
             _run_all(E, g, G, f"R={R}", variants=[1, 3, 4, 5])
 
 
+@pytest.mark.parametrize("name", ["rmat13", "uniform11", "path300", "cliques"])
+def test_sssp_delta_sweep(gpu_device, name):
+    """Near-far bands of any width (and none) give Dijkstra's distances."""
+    import torch
+    E = _emogi()
+    g = graphs()[name]
+    out = torch.empty(max(1, g.num_vertices), dtype=torch.int32, device="cuda")
+    srcs = _sources(g)
+    exp = {s: oracle.dijkstra(g.row_ptr, g.col, g.weights, s) for s in srcs}
+    with E.Graph(g.row_ptr, g.col.astype(np.uint64), g.weights, symmetric=True) as G:
+        for delta in (0, 1, 7, 64, 256, 100000, 0xFFFFFFFF):
+            G.set_sssp_delta(delta)
+            for v in (0, 3, 5):
+                G.set_variant(v)
+                for s in srcs:
+                    G.sssp(s, out)
+                    np.testing.assert_array_equal(E.to_u32(out)[: g.num_vertices], exp[s],
+                                                  err_msg=f"{name} delta={delta} V{v} src={s}")
+        G.set_sssp_delta(64)
+        G.set_scheduler("probe")
+        G.sssp(srcs[-1], out)
+        np.testing.assert_array_equal(E.to_u32(out)[: g.num_vertices], exp[srcs[-1]])
+
+
+@pytest.mark.parametrize("name", ["rmat13", "uniform11", "cliques", "edgeless7", "star5000", "tree1000"])
+def test_cc_both_algorithms(gpu_device, name):
+    """Min-label propagation and sampled union-find give the same min-id labels."""
+    import torch
+    E = _emogi()
+    g = graphs()[name]
+    out = torch.empty(max(1, g.num_vertices), dtype=torch.int32, device="cuda")
+    exp = oracle.cc(g.row_ptr, g.col)
+    for cb in (4, 8):
+        rp, col, w = _with_col(g, cb)
+        with E.Graph(rp, col, w, symmetric=True) as G:
+            for algo in ("label_propagation", "sampled_union_find"):
+                G.set_cc_algorithm(algo)
+                for v in VARIANTS:
+                    G.set_variant(v)
+                    G.cc(out)
+                    np.testing.assert_array_equal(E.to_u32(out)[: g.num_vertices], exp,
+                                                  err_msg=f"{name} {algo} V{v} e={cb}")
+            G.set_scheduler("probe")
+            G.cc(out)
+            np.testing.assert_array_equal(E.to_u32(out)[: g.num_vertices], exp)
+
+
+@pytest.mark.parametrize("name", ["rmat13", "uniform11", "star5000", "path300", "single", "cliques"])
+def test_ordered_frontier(gpu_device, name):
+    E = _emogi()
+    g = graphs()[name]
+    rp, col, w = _with_col(g, 8)
+    with E.Graph(rp, col, w, symmetric=True) as G:
+        G.set_frontier_order(True)
+        G.set_cc_algorithm("label_propagation")
+        _run_all(E, g, G, f"ordered/{name}", variants=[0, 2, 3, 5])
+        G.set_sssp_delta(0)
+        _run_all(E, g, G, f"ordered-nodelta/{name}", algos=("sssp",), variants=[3, 5])
+
+
+def test_directed_sssp_delta(gpu_device):
+    import torch
+    E = _emogi()
+    g = _directed()
+    out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+    with E.Graph(g.row_ptr, g.col, g.weights) as G:
+        for delta in (1, 50, 1000):
+            G.set_sssp_delta(delta)
+            for s in (0, 17, 2999):
+                G.sssp(s, out)
+                np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(g.row_ptr, g.col, g.weights, s))
+
+
 def test_schedulers_agree(gpu_device):
     E = _emogi()
     g = graphs()["rmat13"]
