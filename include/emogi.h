@@ -164,7 +164,7 @@ emogi_status_t emogi_set_scheduler(emogi_graph_t g, int mode);
  * distance is below the current split joins the next frontier, otherwise it
  * waits in a far pile; when the near frontier empties the split moves to the
  * smallest waiting distance + delta.  0 disables the bands (every improved
- * vertex re-enters at once).  Default 8.  Results are identical for any
+ * vertex re-enters at once).  Default 4.  Results are identical for any
  * value; only the amount of re-expansion changes. */
 emogi_status_t emogi_set_sssp_delta(emogi_graph_t g, uint32_t delta);
 /* CC algorithm (both give every vertex the smallest id of its component):

@@ -132,7 +132,8 @@ static void release(emogi_graph_s *g) {
     if (p.degree_hist) (void)hipFree(p.degree_hist);
     for (void *x : {(void *)p.snap_state, (void *)p.snap_stamp, (void *)p.snap_bitmap, (void *)p.far[0],
                     (void *)p.far[1], (void *)p.farbits, (void *)p.snap_farbits, (void *)p.cc_probe,
-                    (void *)p.nextbits})
+                    (void *)p.nextbits, (void *)p.mid[0], (void *)p.mid[1], (void *)p.midbits,
+                    (void *)p.snap_midbits})
         if (x) (void)hipFree(x);
     if (g->mlp_params) (void)hipFree(g->mlp_params);
     BatchPool &b = g->batch;

@@ -33,6 +33,7 @@ enum Counter : int {
     C_VERTS = 4,     // expanded vertices
     C_FAR = 5,       // SSSP: entries appended to the far pile
     C_FARMIN = 6,    // SSSP: smallest live distance in the far pile
+    C_MID = 7,       // SSSP: entries appended to the mid pile
     C_COUNT = 8
 };
 
@@ -52,6 +53,9 @@ struct Pool {
     uint32_t *far[2] = {nullptr, nullptr};    // SSSP near-far: far piles (V entries each)
     uint32_t *farbits = nullptr;              // SSSP near-far: in-far-pile bit per vertex
     uint32_t *snap_farbits = nullptr;
+    uint32_t *mid[2] = {nullptr, nullptr};    // SSSP near-far: mid piles (V entries each)
+    uint32_t *midbits = nullptr;              // SSSP near-far: in-mid-pile bit per vertex
+    uint32_t *snap_midbits = nullptr;
     uint32_t *cc_probe = nullptr;             // CC: roots of probed vertices
     uint32_t *nextbits = nullptr;             // ordered frontier bitmap
     size_t chunk_cap = 0;
@@ -86,7 +90,7 @@ struct emogi_graph_s {
     enum Kind { NONE, DEVICE, PINNED, MANAGED, BORROWED } col_kind = NONE, w_kind = NONE;
 
     uint32_t request_unit = 256;
-    uint32_t sssp_delta = 8;       // near-far band width; 0 = plain label correcting
+    uint32_t sssp_delta = 4;       // near-far band width; 0 = plain label correcting
     bool cc_sampled = true;        // CC by sampled union-find (else min-label propagation)
     bool ordered_frontier = true;  // list each next frontier in ascending id order
     int sched_mode = EMOGI_SCHED_HEURISTIC;

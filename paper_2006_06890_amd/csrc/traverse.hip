@@ -62,6 +62,9 @@ struct OpArgs {
     uint32_t split;     // SSSP near-far: improvements at or above it go to the far pile
     uint32_t *far;      // SSSP: far pile (append at ctr[C_FAR])
     uint32_t *farbits;  // SSSP: one bit per vertex already in the far pile
+    uint32_t mid_limit; // SSSP: improvements in [split, mid_limit) go to the mid pile
+    uint32_t *mid;      // SSSP: mid pile (append at ctr[C_MID])
+    uint32_t *midbits;  // SSSP: one bit per vertex already in the mid pile
     uint32_t *nextbits; // ordered frontier: next frontier as a bitmap (null: LDS-staged queue)
     unsigned long long *ctr;
 };
@@ -118,8 +121,10 @@ __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v,
         uint32_t old = atomicMin(&a.state[v], uint32_t(nd));
         if (old <= uint32_t(nd)) return 0;
         if (uint32_t(nd) >= a.split) {
-            // beyond the current distance band: park it in the far pile once
+            // beyond the current band: park it once in the mid pile (the next
+            // few bands) or, further out, in the far pile
             const uint32_t bit = 1u << (v & 31u);
+            if (uint32_t(nd) < a.mid_limit) return (atomicOr(&a.midbits[v >> 5], bit) & bit) ? 0 : 3;
             return (atomicOr(&a.farbits[v >> 5], bit) & bit) ? 0 : 2;
         }
         return atomicExch(&a.stamp[v], a.tag) != a.tag ? 1 : 0;
@@ -153,6 +158,13 @@ __device__ __forceinline__ void emit(Stage &st, int r, uint32_t v, uint32_t *nex
             if (lane == 0) base = uint32_t(atomicAdd(&a.ctr[C_FAR], (unsigned long long)__popcll(m)));
             base = __shfl(base, 0);
             if (r == 2) a.far[base + rank_below(m)] = v;
+        }
+        const uint64_t mm = __ballot(r == 3);
+        if (mm) {
+            uint32_t base = 0;
+            if (lane == 0) base = uint32_t(atomicAdd(&a.ctr[C_MID], (unsigned long long)__popcll(mm)));
+            base = __shfl(base, 0);
+            if (r == 3) a.mid[base + rank_below(mm)] = v;
         }
     }
 }
@@ -534,29 +546,35 @@ __device__ __forceinline__ void push_ballot(bool p, uint32_t v, uint32_t *dst, u
     if (p) dst[base + rank_below(m)] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_far_split(const uint32_t *far, uint64_t n, const uint32_t *dist,
-                                                       uint32_t old_split, uint32_t new_split,
-                                                       uint32_t *farbits, uint32_t *nearq,
-                                                       uint32_t *far_out, unsigned long long *ctr) {
+// Cuts a pile at `cut`: entries below `stale` are dropped (already settled),
+// entries in [stale, cut) move to `dst` (marking `dst_bits` when given),
+// the rest are compacted into `keep`.  Moved and dropped entries leave
+// `src_bits`.
+__global__ __launch_bounds__(kBlock) void k_far_split(const uint32_t *pile, uint64_t n, const uint32_t *dist,
+                                                       uint32_t stale, uint32_t cut, uint32_t *src_bits,
+                                                       uint32_t *dst_bits, uint32_t *dst, int dst_ctr,
+                                                       uint32_t *keep_out, int keep_ctr,
+                                                       unsigned long long *ctr) {
     const int lane = lane_id();
     const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
     // whole waves step together so the ballots see every lane
     for (uint64_t i0 = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); i0 < n; i0 += stride) {
         const uint64_t i = i0 + lane;
-        bool to_near = false, keep = false;
+        bool move = false, keep = false;
         uint32_t v = 0;
         if (i < n) {
-            v = far[i];
+            v = pile[i];
             const uint32_t d = dist[v];
-            if (d < new_split) {
-                atomicAnd(&farbits[v >> 5], ~(1u << (v & 31u)));
-                to_near = d >= old_split;
+            if (d < cut) {
+                atomicAnd(&src_bits[v >> 5], ~(1u << (v & 31u)));
+                move = d >= stale;
+                if (move && dst_bits) atomicOr(&dst_bits[v >> 5], 1u << (v & 31u));
             } else {
                 keep = true;
             }
         }
-        push_ballot(to_near, v, nearq, &ctr[C_NEXT], lane);
-        push_ballot(keep, v, far_out, &ctr[C_FAR], lane);
+        push_ballot(move, v, dst, &ctr[dst_ctr], lane);
+        push_ballot(keep, v, keep_out, &ctr[keep_ctr], lane);
     }
 }
 
@@ -715,7 +733,13 @@ static emogi_status_t ensure_pool(emogi_graph_s *g, int algo) {
         for (int i = 0; i < 2; ++i)
             if ((st = dalloc(reinterpret_cast<void **>(&p.far[i]), V * sizeof(uint32_t))) != EMOGI_OK)
                 return st;
+        for (int i = 0; i < 2; ++i)
+            if ((st = dalloc(reinterpret_cast<void **>(&p.mid[i]), V * sizeof(uint32_t))) != EMOGI_OK)
+                return st;
         if ((st = dalloc(reinterpret_cast<void **>(&p.farbits), ((V + 31) / 32) * sizeof(uint32_t))) !=
+            EMOGI_OK)
+            return st;
+        if ((st = dalloc(reinterpret_cast<void **>(&p.midbits), ((V + 31) / 32) * sizeof(uint32_t))) !=
             EMOGI_OK)
             return st;
     }
@@ -820,6 +844,13 @@ static emogi_status_t snapshot(emogi_graph_s *g, int algo, uint32_t *out, hipStr
             return EMOGI_E_OOM_DEVICE;
         }
         EMOGI_HIP_TRY(cp(p.farbits, p.snap_farbits, words * 4), EMOGI_E_HIP);
+        if (!p.snap_midbits && hipMalloc(&p.snap_midbits, words * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            p.snap_midbits = nullptr;
+            set_error("probe snapshot allocation failed");
+            return EMOGI_E_OOM_DEVICE;
+        }
+        EMOGI_HIP_TRY(cp(p.midbits, p.snap_midbits, words * 4), EMOGI_E_HIP);
     }
     return EMOGI_OK;
 }
@@ -930,7 +961,11 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
 
     uint64_t cap = V + 2;
     if (const char *env = getenv("EMOGI_MAX_ITERS")) cap = std::min<uint64_t>(cap, strtoull(env, nullptr, 10));
-    const uint32_t align_elems = std::max<uint32_t>(1, g->request_unit / g->col_bytes);
+    // Round list starts so each wave load covers whole request units of every
+    // array it reads: SSSP also reads the 4-byte weights at the same indices,
+    // so it aligns to R / 4 elements (8-byte ids then span two units).
+    const uint32_t elem_bytes = (algo == A_SSSP) ? 4u : g->col_bytes;
+    const uint32_t align_elems = std::max<uint32_t>(1, g->request_unit / elem_bytes);
     int cur = 0;
     uint32_t iter = 0;
     bool overflow_seen = false;
@@ -951,36 +986,70 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     uint32_t split = nearfar ? delta : 0xFFFFFFFFu;
     uint64_t far_n = 0;
     int fcur = 0;
-    if (nearfar)
+    if (nearfar) {
         EMOGI_HIP_TRY(hipMemsetAsync(p.farbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
-    while (n > 0 || far_n > 0) {
+        EMOGI_HIP_TRY(hipMemsetAsync(p.midbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
+    }
+    // mid pile: the next kMidBands bands, so the large far pile is re-read
+    // only when the mid pile runs dry
+    const uint64_t kMidBands = 16;
+    uint32_t mid_limit = nearfar ? uint32_t(std::min<uint64_t>(uint64_t(split) + kMidBands * delta, 0xFFFFFFFFull))
+                                 : 0xFFFFFFFFu;
+    uint64_t mid_n = 0;
+    int mcur = 0;
+    // smallest live (>= split) distance in a pile, or ~0 when none
+    auto pile_min = [&](const uint32_t *pile, uint64_t len, unsigned long long *m) -> emogi_status_t {
+        EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
+        EMOGI_HIP_TRY(hipMemsetAsync(&p.counters[C_FARMIN], 0xFF, sizeof(unsigned long long), stream),
+                      EMOGI_E_HIP);
+        hipLaunchKernelGGL(k_far_min, dim3(fill_grid(len)), dim3(kBlock), 0, stream, pile, len, out, split,
+                           p.counters);
+        EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, stream),
+                      EMOGI_E_HIP);
+        EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+        *m = p.host_counters[C_FARMIN];
+        return EMOGI_OK;
+    };
+    auto pile_cut = [&](const uint32_t *pile, uint64_t len, uint32_t cut, uint32_t *src_bits, uint32_t *dst_bits,
+                        uint32_t *dst, int dst_ctr, uint32_t *keep, int keep_ctr) -> emogi_status_t {
+        EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
+        hipLaunchKernelGGL(k_far_split, dim3(fill_grid(len)), dim3(kBlock), 0, stream, pile, len, out, split, cut,
+                           src_bits, dst_bits, dst, dst_ctr, keep, keep_ctr, p.counters);
+        EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+        EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, stream),
+                      EMOGI_E_HIP);
+        EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+        return EMOGI_OK;
+    };
+    while (n > 0 || mid_n > 0 || far_n > 0) {
         if (n == 0) {
-            // near frontier exhausted: re-cut the far pile at (live minimum + delta)
-            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
-                          EMOGI_E_HIP);
-            EMOGI_HIP_TRY(hipMemsetAsync(&p.counters[C_FARMIN], 0xFF, sizeof(unsigned long long), stream),
-                          EMOGI_E_HIP);
-            hipLaunchKernelGGL(k_far_min, dim3(fill_grid(far_n)), dim3(kBlock), 0, stream, p.far[fcur], far_n,
-                               out, split, p.counters);
-            EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
-                                         hipMemcpyDeviceToHost, stream),
-                          EMOGI_E_HIP);
-            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
-            const unsigned long long m = p.host_counters[C_FARMIN];
-            const uint64_t ns64 = m == ~0ull ? uint64_t(split) : std::min<uint64_t>(m + delta, 0xFFFFFFFFull);
+            // near frontier exhausted: refill the mid pile from the far pile if
+            // needed, then cut the mid pile at (live minimum + delta)
+            unsigned long long m;
+            if (mid_n == 0) {
+                if ((st = pile_min(p.far[fcur], far_n, &m)) != EMOGI_OK) return st;
+                const uint32_t new_mid = m == ~0ull ? split
+                    : uint32_t(std::min<uint64_t>(m + kMidBands * delta, 0xFFFFFFFFull));
+                if ((st = pile_cut(p.far[fcur], far_n, new_mid, p.farbits, p.midbits, p.mid[mcur], C_MID,
+                                   p.far[fcur ^ 1], C_FAR)) != EMOGI_OK)
+                    return st;
+                far_n = p.host_counters[C_FAR];
+                mid_n = p.host_counters[C_MID];
+                fcur ^= 1;
+                mid_limit = std::max(mid_limit, new_mid);
+                if (mid_n == 0) continue;
+            }
+            if ((st = pile_min(p.mid[mcur], mid_n, &m)) != EMOGI_OK) return st;
+            const uint64_t ns64 = m == ~0ull ? uint64_t(split) : std::min<uint64_t>(m + delta, mid_limit);
             const uint32_t new_split = uint32_t(std::max<uint64_t>(ns64, split));
-            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
-                          EMOGI_E_HIP);
-            hipLaunchKernelGGL(k_far_split, dim3(fill_grid(far_n)), dim3(kBlock), 0, stream, p.far[fcur], far_n,
-                               out, split, new_split, p.farbits, p.queue[cur], p.far[fcur ^ 1], p.counters);
-            EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
-            EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
-                                         hipMemcpyDeviceToHost, stream),
-                          EMOGI_E_HIP);
-            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+            if ((st = pile_cut(p.mid[mcur], mid_n, new_split, p.midbits, nullptr, p.queue[cur], C_NEXT,
+                               p.mid[mcur ^ 1], C_MID)) != EMOGI_OK)
+                return st;
             n = p.host_counters[C_NEXT];
-            far_n = p.host_counters[C_FAR];
-            fcur ^= 1;
+            mid_n = p.host_counters[C_MID];
+            mcur ^= 1;
             split = new_split;
             continue;
         }
@@ -1013,6 +1082,9 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             a.ctr = p.counters;
             a.split = split;
             a.far = nearfar ? p.far[fcur] + far_n : nullptr;
+            a.mid = nearfar ? p.mid[mcur] + mid_n : nullptr;
+            a.midbits = p.midbits;
+            a.mid_limit = mid_limit;
             a.farbits = p.farbits;
             a.nextbits = ordered ? p.nextbits : nullptr;
             EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
@@ -1101,6 +1173,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         if (hc[C_OVERFLOW]) overflow_seen = true;
         n = hc[C_NEXT];
         far_n += hc[C_FAR];
+        mid_n += hc[C_MID];
         if (identity) {
             identity = false;
             cur = 0;

@@ -334,9 +334,14 @@ def test_stats_account_for_edges(gpu_device):
             assert st["iterations"] == int(lv[lv != E.INF].max()) + 1
             mask = (lv != E.INF).astype(np.uint8)
             assert st["request_bytes"] == oracle.request_bytes(g.row_ptr, 4, st["request_unit"], mask)
+        G.set_cc_algorithm("label_propagation")
         G.cc(out)
         st = G.stats()
         assert st["edges_scanned"] >= g.num_edges  # round 1 streams every list
+        G.set_cc_algorithm("sampled_union_find")
+        G.cc(out)
+        st = G.stats()
+        assert st["edges_scanned"] < g.num_edges   # only lists outside the large tree
 
 
 def test_managed_or_unsupported(gpu_device):
