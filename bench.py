@@ -16,6 +16,15 @@ The JSON line also carries the host-link rate of the neighbour-scan kernels
 against the measured pinned memcpy peak, the HBM and managed placements run
 once after the timed region, the roofline of the dominant kernel and the
 oracle's CPU rate on a bounded sample.
+
+Other workloads (``--config``):
+  kron16     R-MAT scale 16, uint32 ids, BFS only from the lowest-id vertex
+             with degree > 0 (the small single-source case);
+  uniform27  uniform random graph, 2^27 vertices, 2^27 * 32 samples
+             (~8.6 billion directed edges), uint32 ids + uint32 weights;
+  batched26  R-MAT scale 26, uint32 ids + weights: one step = 64 BFS sources
+             (degrees log-spaced 1..max, seed 4) in one batched call plus 64
+             SSSP sources (seed 5) in another, against 64 plain runs of each.
 """
 import argparse
 import json
@@ -31,6 +40,25 @@ PCIE5_X16_GBPS = 64.0  # published per-direction rate of the MI355X host link (P
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+PRESETS = {
+    "kron27": dict(workload="kron", scale=27, col_bytes=8, sources=8, steps=8, cpu_scale=24,
+                   algos=("bfs", "sssp", "cc")),
+    "kron16": dict(workload="kron", scale=16, col_bytes=4, sources=1, steps=50, cpu_scale=16,
+                   algos=("bfs",)),
+    "uniform27": dict(workload="uniform", scale=27, col_bytes=4, sources=8, steps=8, cpu_scale=22,
+                      algos=("bfs", "sssp", "cc")),
+    "batched26": dict(workload="kron", scale=26, col_bytes=4, sources=64, steps=2, cpu_scale=22,
+                      algos=("bfs", "sssp")),
+}
+
+
+def workload_name(args):
+    kind = "Kronecker/R-MAT" if args.workload == "kron" else "uniform random"
+    size = f"scale {args.scale}, edgefactor 16" if args.workload == "kron" else \
+        f"2^{args.scale} vertices, 2^{args.scale} x 32 samples"
+    return f"{kind} {size}, u{8 * args.col_bytes} col + u32 weights in pinned host zero-copy memory"
 
 
 def build_graph(args, E, graphgen):
@@ -52,15 +80,15 @@ def build_graph(args, E, graphgen):
     return rp, col, w
 
 
-def run_step(G, src, out, torch):
-    """BFS + SSSP from src, CC; returns per-algorithm stats."""
+def run_step(G, src, out, algos=("bfs", "sssp", "cc")):
+    """The step's traversals (BFS, SSSP from src; CC); per-algorithm stats."""
     res = {}
-    G.bfs(src, out)
-    res["bfs"] = G.stats()
-    G.sssp(src, out)
-    res["sssp"] = G.stats()
-    G.cc(out)
-    res["cc"] = G.stats()
+    for a in algos:
+        if a == "cc":
+            G.cc(out)
+        else:
+            getattr(G, a)(src, out)
+        res[a] = G.stats()
     return res
 
 
@@ -75,7 +103,8 @@ def kernel_key(algo, variant, col_bytes):
 
 KERNEL_SOURCES = ["paper_2006_06890_amd/csrc/traverse.hip", "paper_2006_06890_amd/csrc/wave.h",
                   "paper_2006_06890_amd/csrc/internal.h"]
-COUNTERS = os.path.join(ROOT, "profiles", "counters_kron27_u64.json")
+def counters_path(args):
+    return os.path.join(ROOT, "profiles", f"counters_{args.config}_u{8 * args.col_bytes}.json")
 
 
 def kernel_sources_sha1():
@@ -86,12 +115,13 @@ def kernel_sources_sha1():
     return h.hexdigest()
 
 
-def counter_traffic(kernel):
+def counter_traffic(args, kernel):
     """Per-dispatch bytes from the committed rocprofv3 counter runs, or None
     when the kernel sources changed since they were taken."""
-    if not os.path.exists(COUNTERS):
+    path = counters_path(args)
+    if not os.path.exists(path):
         return None
-    c = json.load(open(COUNTERS))
+    c = json.load(open(path))
     if c.get("kernel_sources_sha1") != kernel_sources_sha1() or kernel not in c["kernels"]:
         return None
     return c["kernels"][kernel]
@@ -99,41 +129,59 @@ def counter_traffic(kernel):
 
 def cpu_baseline(args):
     """The oracle, as it stands, on a bounded sample of the same workload."""
-    import numpy as np
     import graphgen
     import oracle
     scale = args.cpu_scale
-    g = graphgen.rmat(scale, 16, 0.57, 0.19, 0.19, seed=1).to_csr(args.col_bytes, weights=True)
-    src = graphgen.random_sources(g, 1, seed=2)[0]
-    t = time.perf_counter()
-    lv = oracle.bfs(g.row_ptr, g.col, src)
-    t_bfs = time.perf_counter() - t
-    t = time.perf_counter()
-    oracle.dijkstra(g.row_ptr, g.col, g.weights, src)
-    t_sssp = time.perf_counter() - t
-    t = time.perf_counter()
-    oracle.cc(g.row_ptr, g.col)
-    t_cc = time.perf_counter() - t
+    if args.workload == "kron":
+        h = graphgen.rmat(scale, 16, 0.57, 0.19, 0.19, seed=1)
+        kind = f"R-MAT scale {scale}"
+    else:
+        h = graphgen.uniform(scale, (1 << scale) * 32, seed=1)
+        kind = f"uniform random 2^{scale} vertices, 2^{scale} x 32 samples"
+    g = h.to_csr(args.col_bytes, weights=True)
+    h.free()
+    if args.config == "kron16":
+        src = int((g.degrees() > 0).argmax())
+    else:
+        src = graphgen.random_sources(g, 1, seed=2)[0]
+    times = {a: 0.0 for a in args.algos}
+    lv = None
+    reps = 0
+    while reps == 0 or sum(times.values()) < 5.0:  # small samples are repeated to >= 5 s
+        for a in args.algos:
+            t = time.perf_counter()
+            if a == "bfs":
+                lv = oracle.bfs(g.row_ptr, g.col, src)
+            elif a == "sssp":
+                oracle.dijkstra(g.row_ptr, g.col, g.weights, src)
+            else:
+                oracle.cc(g.row_ptr, g.col)
+            times[a] += time.perf_counter() - t
+        reps += 1
+    if lv is None:
+        lv = oracle.bfs(g.row_ptr, g.col, src)
     reached = oracle.reached_edges(g.row_ptr, lv)
-    edges = 2 * reached + g.num_edges
-    secs = t_bfs + t_sssp + t_cc
+    edges = reps * sum(g.num_edges if a == "cc" else reached for a in args.algos)
+    secs = sum(times.values())
+    names = {"bfs": "queue BFS", "sssp": "binary-heap Dijkstra", "cc": "union-find CC"}
     return {
         "value": edges / secs / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-        "sample": (f"single-threaded oracle (queue BFS + binary-heap Dijkstra + union-find CC) on "
-                   f"R-MAT scale {scale} from the same generator and seeds, one source; "
-                   f"{secs:.1f}s of CPU (bfs {t_bfs:.1f}s, sssp {t_sssp:.1f}s, cc {t_cc:.1f}s)"),
+        "sample": (f"single-threaded oracle ({' + '.join(names[a] for a in args.algos)}) on "
+                   f"{kind} from the same generator and seeds, one source, {reps} repetition(s); {secs:.1f}s of CPU ("
+                   + ", ".join(f"{a} {t:.1f}s" for a, t in times.items()) + ")"),
     }
 
 
-def main():
+def parse_args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: per config)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["kron", "uniform"], default="kron")
-    ap.add_argument("--scale", type=int, default=27)
-    ap.add_argument("--col-bytes", type=int, choices=[4, 8], default=8)
-    ap.add_argument("--sources", type=int, default=8)
+    ap.add_argument("--config", choices=sorted(PRESETS), default="kron27",
+                    help="workload preset (default: R-MAT scale 27, uint64 ids)")
+    ap.add_argument("--scale", type=int, default=None)
+    ap.add_argument("--col-bytes", type=int, choices=[4, 8], default=None)
+    ap.add_argument("--sources", type=int, default=None)
     ap.add_argument("--scheduler", default="heuristic")
     ap.add_argument("--request-unit", type=int, default=256)
     ap.add_argument("--no-arms", action="store_true", help="skip the HBM/managed comparison runs")
@@ -141,72 +189,101 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-source batched runs")
     ap.add_argument("--noncoherent", action="store_true", help="pin the edge arrays non-coherent")
     ap.add_argument("--no-learned", action="store_true", help="skip the scheduler comparison")
-    ap.add_argument("--cpu-scale", type=int, default=24)
+    ap.add_argument("--no-autotune", action="store_true", help="batched26: keep the default batch parameters")
+    ap.add_argument("--cpu-scale", type=int, default=None)
     ap.add_argument("--calib-bytes", type=int, default=1 << 30)
     ap.add_argument("--calibrate-only", action="store_true",
                     help="run the link calibration (plain zero-copy read kernels) and exit")
     args = ap.parse_args()
+    preset = PRESETS[args.config]
+    args.workload = preset["workload"]
+    args.algos = preset["algos"]
+    for k in ("scale", "col_bytes", "sources", "steps", "cpu_scale"):
+        if getattr(args, k) is None:
+            setattr(args, k, preset[k])
+    return args
 
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
-    import torch
-    import graphgen
-    import paper_2006_06890_amd as E
+def base_result(args, value, elapsed, V, M, profile):
+    return {
+        "metric": "GTEPS and achieved host-link GB/s (% of measured pinned peak), zero-copy vs managed",
+        "value": round(value, 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000 * elapsed / max(1, args.steps), 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded graph generator; no dataset)",
+        "config": {
+            "workload": workload_name(args) + "; " + "+".join(a.upper() for a in args.algos) + " per step",
+            "preset": args.config, "vertices": V, "directed_edges": M, "col_bytes": args.col_bytes,
+            "placement": "host_zero_copy", "request_unit": args.request_unit,
+        },
+        "host_link": {
+            "pinned_memcpy_peak_GBps": round(profile["memcpy_GBps"], 2),
+            "request_unit_measured": profile["request_unit"],
+            "kernel_seq_read_GBps": round(max(profile["seq_read_GBps"].values()), 2),
+            "latency_us": round(profile["latency_us"], 3),
+        },
+    }
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    E.lib()
-    # Link calibration (hot-path row a0): memcpy peak, kernel read rates, R, latency.
-    profile = E.calibrate_link(args.calib_bytes)
+
+def roofline(args, kernels, peak):
+    """The dominant kernel: algorithmic link bytes per launch over its
+    average HIP-event launch time, against the link's published rate."""
+    dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["ms"])
+    achieved = dom["bytes"] / (dom["ms"] * 1e6)
+    r = {
+        "bound": "host_link",
+        "kernel": dom_name,
+        "achieved": round(achieved, 2),
+        "peak": PCIE5_X16_GBPS,
+        "unit": "GB/s",
+        "frac": round(achieved / PCIE5_X16_GBPS, 4),
+        "frac_of_measured_memcpy": round(achieved / peak, 4),
+        "traffic": None,
+        "launches": dom["launches"],
+        "avg_launch_ms": round(dom["ms"] / max(1, dom["launches"]), 4),
+        "algorithmic_bytes_per_launch": round(dom["bytes"] / max(1, dom["launches"])),
+    }
+    ct = counter_traffic(args, dom_name)
+    if ct is not None:
+        # host-link bytes per launch from TCC_EA0_RDREQ_IO_32B x 32 B (copy-kernel factor applied);
+        # FETCH_SIZE (scaled) + WRITE_SIZE per launch beside it for the HBM side
+        r["traffic"] = round(ct["link_bytes_per_dispatch"])
+        r["traffic_fetch_write"] = round(ct["fetch_bytes_per_dispatch_scaled"] + ct["write_bytes_per_dispatch"])
+        r["traffic_source"] = os.path.relpath(counters_path(args), ROOT)
+    return r
+
+
+def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
+    V, M = rp.shape[0] - 1, int(rp[-1])
     peak = profile["memcpy_GBps"]
-    log(f"[bench] link: memcpy {peak:.2f} GB/s, seq read {profile['seq_read_GBps']}, "
-        f"R {profile['request_unit']} B, latency {profile['latency_us']:.2f} us")
-    if args.calibrate_only:
-        print(json.dumps({"link_profile": profile}), flush=True)
-        return
-    os.environ.setdefault("GG_VERBOSE", "1")  # generator prints its phases (progress)
-
-    rp, col, w = build_graph(args, E, graphgen)
-    V = rp.shape[0] - 1
-    M = int(rp[-1])
-    csr = graphgen.CSR(rp, col.array)
-    sources = graphgen.random_sources(csr, args.sources, seed=2)
-    out = torch.empty(V, dtype=torch.int32, device="cuda")
-
-    G = E.Graph(rp, col, w, placement="host_zero_copy", symmetric=True, borrow=True)
-    G.set_request_unit(args.request_unit)
-    if args.scheduler.isdigit():
-        G.set_variant(int(args.scheduler))
-    else:
-        G.set_scheduler(args.scheduler)
-
     for i in range(args.warmup):
-        run_step(G, sources[i % len(sources)], out, torch)
+        run_step(G, sources[i % len(sources)], out, args.algos)
         log(f"[bench] warmup step {i} done")
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps = []
     for i in range(args.steps):
-        steps.append((sources[i % len(sources)], run_step(G, sources[i % len(sources)], out, torch)))
+        steps.append((sources[i % len(sources)], run_step(G, sources[i % len(sources)], out, args.algos)))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for i, (s, r) in enumerate(steps):
-        log(f"[bench] step {i} src={s}: bfs {r['bfs']['total_ms']:.1f} ms, sssp {r['sssp']['total_ms']:.1f} ms, "
-            f"cc {r['cc']['total_ms']:.1f} ms")
+        log(f"[bench] step {i} src={s}: " + ", ".join(f"{a} {r[a]['total_ms']:.1f} ms" for a in r))
 
     # --- throughput ---
     teps_edges = 0
-    per = {a: {"ms": 0.0, "edges": 0, "scan_ms": 0.0, "bytes": 0} for a in ("bfs", "sssp", "cc")}
+    per = {a: {"ms": 0.0, "edges": 0, "scan_ms": 0.0, "bytes": 0} for a in args.algos}
     kernels = {}
     for s, r in steps:
         reached = r["bfs"]["edges_scanned"]  # BFS expands every reached vertex once
-        for a in ("bfs", "sssp", "cc"):
+        for a in args.algos:
             st = r[a]
             e = M if a == "cc" else reached
             teps_edges += e
@@ -225,71 +302,22 @@ def main():
     link_bytes = sum(p["bytes"] for p in per.values())
     scan_ms = sum(p["scan_ms"] for p in per.values())
     link_gbps = link_bytes / (scan_ms * 1e6) if scan_ms else 0.0
-    dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["ms"])
-    achieved = dom["bytes"] / (dom["ms"] * 1e6)
 
-    result = {
-        "metric": "GTEPS and achieved host-link GB/s (% of measured pinned peak), zero-copy vs managed",
-        "value": round(value, 4),
-        "unit": "GTEPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1000 * elapsed / max(1, args.steps), 2),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic (seeded R-MAT generator; no dataset)",
-        "config": {
-            "workload": (f"{'Kronecker/R-MAT' if args.workload == 'kron' else 'uniform'} scale {args.scale}, "
-                         f"edgefactor 16, u{8 * args.col_bytes} col + u32 weights in pinned host "
-                         f"zero-copy memory; BFS+SSSP+CC per step"),
-            "vertices": V, "directed_edges": M, "col_bytes": args.col_bytes,
-            "placement": "host_zero_copy", "sources": sources, "scheduler": args.scheduler,
-            "request_unit": args.request_unit,
-        },
-        "per_algorithm": {
-            a: {"gteps": round(p["edges"] / (p["ms"] * 1e6), 4) if p["ms"] else None,
-                "link_GBps": round(p["bytes"] / (p["scan_ms"] * 1e6), 2) if p["scan_ms"] else None,
-                "ms_per_run": round(p["ms"] / len(steps), 2)}
-            for a, p in per.items()
-        },
-        "host_link": {
-            "scan_GBps": round(link_gbps, 2),
-            "pinned_memcpy_peak_GBps": round(peak, 2),
-            "pct_of_pinned_peak": round(100 * link_gbps / peak, 1),
-            "request_unit_measured": profile["request_unit"],
-            "kernel_seq_read_GBps": round(max(profile["seq_read_GBps"].values()), 2),
-            "latency_us": round(profile["latency_us"], 3),
-        },
-        "roofline": {
-            "bound": "host_link",
-            "kernel": dom_name,
-            "achieved": round(achieved, 2),
-            "peak": PCIE5_X16_GBPS,
-            "unit": "GB/s",
-            "frac": round(achieved / PCIE5_X16_GBPS, 4),
-            "frac_of_measured_memcpy": round(achieved / peak, 4),
-            "traffic": None,
-            "launches": dom["launches"],
-            "avg_launch_ms": round(dom["ms"] / max(1, dom["launches"]), 4),
-            "algorithmic_bytes_per_launch": round(dom["bytes"] / max(1, dom["launches"])),
-        },
+    result = base_result(args, value, elapsed, V, M, profile)
+    result["config"].update(sources=sources, scheduler=args.scheduler)
+    result["per_algorithm"] = {
+        a: {"gteps": round(p["edges"] / (p["ms"] * 1e6), 4) if p["ms"] else None,
+            "link_GBps": round(p["bytes"] / (p["scan_ms"] * 1e6), 2) if p["scan_ms"] else None,
+            "ms_per_run": round(p["ms"] / len(steps), 3)}
+        for a, p in per.items()
     }
-    ct = counter_traffic(dom_name)
-    if ct is not None:
-        # host-link bytes per launch from TCC_EA0_RDREQ_IO_32B x 32 B (copy-kernel factor applied);
-        # FETCH_SIZE (scaled) + WRITE_SIZE per launch beside it for the HBM side
-        result["roofline"]["traffic"] = round(ct["link_bytes_per_dispatch"])
-        result["roofline"]["traffic_fetch_write"] = round(ct["fetch_bytes_per_dispatch_scaled"]
-                                                          + ct["write_bytes_per_dispatch"])
-        result["roofline"]["traffic_source"] = "profiles/counters_kron27_u64.json"
+    result["host_link"].update(scan_GBps=round(link_gbps, 2), pct_of_pinned_peak=round(100 * link_gbps / peak, 1))
+    result["roofline"] = roofline(args, kernels, peak)
 
     # --- the two systems patterns, each against the plain method on this GPU ---
-    plain_bfs_ms = per["bfs"]["ms"] / len(steps)
-    plain_sssp_ms = per["sssp"]["ms"] / len(steps)
-    if not args.no_batch:
+    if not args.no_batch and "sssp" in args.algos:
+        plain_bfs_ms = per["bfs"]["ms"] / len(steps)
+        plain_sssp_ms = per["sssp"]["ms"] / len(steps)
         srcs64 = graphgen.degree_spread_sources(rp, 64, seed=4)
         out64 = torch.empty(len(srcs64) * V, dtype=torch.int32, device="cuda")
         G.bfs_batch(srcs64, out64)
@@ -319,9 +347,9 @@ def main():
                 G.set_variant(mode)
             else:
                 G.set_scheduler(mode)
-            r = run_step(G, sources[0], out, torch)
-            sched[name] = {a: round(r[a]["total_ms"], 1) for a in r}
-            sched[name]["step_ms"] = round(sum(r[a]["total_ms"] for a in r), 1)
+            r = run_step(G, sources[0], out, args.algos)
+            sched[name] = {a: round(r[a]["total_ms"], 2) for a in r}
+            sched[name]["step_ms"] = round(sum(r[a]["total_ms"] for a in r), 2)
         result["schedulers"] = sched
         log(f"[bench] schedulers (one step, source {sources[0]}): {sched}")
 
@@ -335,18 +363,140 @@ def main():
                 arms[placement] = {"status": str(e)}
                 continue
             H.set_scheduler("heuristic")
-            r = run_step(H, sources[0], out, torch)
+            r = run_step(H, sources[0], out, args.algos)
             reached = r["bfs"]["edges_scanned"]
             ms = sum(r[a]["total_ms"] for a in r)
             arms[placement] = {
-                "gteps": round((2 * reached + M) / (ms * 1e6), 4),
-                "bfs_gteps": round(reached / (r["bfs"]["total_ms"] * 1e6), 4),
-                "sssp_ms": round(r["sssp"]["total_ms"], 2),
-                "cc_ms": round(r["cc"]["total_ms"], 2),
+                "gteps": round(sum(M if a == "cc" else reached for a in r) / (ms * 1e6), 4),
+                **{f"{a}_ms": round(r[a]["total_ms"], 2) for a in r},
             }
             H.close()
             log(f"[bench] arm {placement}: {arms[placement]}")
         result["arms"] = arms
+    return result
+
+
+def bench_batched(args, E, G, rp, sources, profile, torch):
+    """One step = every BFS source in one batched call + every SSSP source in
+    another; reported against one plain run per source."""
+    import numpy as np
+    V, M = rp.shape[0] - 1, int(rp[-1])
+    bfs_srcs, sssp_srcs = sources
+    out = torch.empty(max(len(bfs_srcs), len(sssp_srcs)) * V, dtype=torch.int32, device="cuda")
+    params = {}
+    for a, srcs in (("bfs", bfs_srcs), ("sssp", sssp_srcs)):
+        if args.no_autotune:
+            params[a] = G.get_batch_params()
+        else:
+            best, trials = G.autotune_batch(a, srcs, out)
+            params[a] = best
+            log(f"[bench] autotuned {a}: {best} over {len(trials)} trials")
+
+    def step():
+        st = {}
+        for a, srcs in (("bfs", bfs_srcs), ("sssp", sssp_srcs)):
+            G.set_batch_params(**params[a])
+            getattr(G, a + "_batch")(srcs, out[:len(srcs) * V])
+            st[a] = G.stats()
+        return st
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup step {i} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # reached edges per source (the TEPS numerator), from the last outputs
+    deg = torch.from_numpy(np.diff(rp).astype(np.int64)).to("cuda")
+    reached = {}
+    for a, srcs in (("bfs", bfs_srcs), ("sssp", sssp_srcs)):
+        getattr(G, a + "_batch")(srcs, out[:len(srcs) * V])
+        o = out[:len(srcs) * V].view(len(srcs), V)
+        reached[a] = [int(((o[i] != -1).to(torch.int64) * deg).sum()) for i in range(len(srcs))]
+    teps_edges = args.steps * (sum(reached["bfs"]) + sum(reached["sssp"]))
+    value = teps_edges / elapsed / 1e9
+
+    # the plain method, one run per source
+    plain = {}
+    G.set_scheduler("heuristic")
+    one = out[:V]
+    for a, srcs in (("bfs", bfs_srcs), ("sssp", sssp_srcs)):
+        ms = 0.0
+        for s in srcs:
+            getattr(G, a)(s, one)
+            ms += G.stats()["total_ms"]
+        plain[a] = ms
+        log(f"[bench] plain {a}: {len(srcs)} runs in {ms:.0f} ms")
+    G.close()
+
+    result = base_result(args, value, elapsed, V, M, profile)
+    result["config"].update(bfs_sources=len(bfs_srcs), sssp_sources=len(sssp_srcs),
+                            source_degrees="log-spaced 1..max (BFS seed 4, SSSP seed 5)",
+                            batch_params=params)
+    result["batched"] = {}
+    for a in ("bfs", "sssp"):
+        ms = sum(r[a]["total_ms"] for r in runs) / len(runs)
+        result["batched"][a] = {
+            "sources": len(reached[a]), "ms_per_call": round(ms, 1),
+            "gteps": round(sum(reached[a]) / (ms * 1e6), 3),
+            "plain_ms_all_sources": round(plain[a], 1),
+            "plain_gteps": round(sum(reached[a]) / (plain[a] * 1e6), 3),
+            "speedup_vs_plain": round(plain[a] / ms, 2),
+            "link_bytes_per_call": runs[-1][a]["useful_link_bytes"],
+        }
+    log(f"[bench] batched: {result['batched']}")
+    return result
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import graphgen
+    import paper_2006_06890_amd as E
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    E.lib()
+    # Link calibration (hot-path row a0): memcpy peak, kernel read rates, R, latency.
+    profile = E.calibrate_link(args.calib_bytes)
+    log(f"[bench] link: memcpy {profile['memcpy_GBps']:.2f} GB/s, seq read {profile['seq_read_GBps']}, "
+        f"R {profile['request_unit']} B, latency {profile['latency_us']:.2f} us")
+    if args.calibrate_only:
+        print(json.dumps({"link_profile": profile}), flush=True)
+        return
+    os.environ.setdefault("GG_VERBOSE", "1")  # generator prints its phases (progress)
+
+    rp, col, w = build_graph(args, E, graphgen)
+    V = rp.shape[0] - 1
+    deg = np.diff(rp)
+    G = E.Graph(rp, col, w, placement="host_zero_copy", symmetric=True, borrow=True)
+    G.set_request_unit(args.request_unit)
+    if args.scheduler.isdigit():
+        G.set_variant(int(args.scheduler))
+    else:
+        G.set_scheduler(args.scheduler)
+
+    if args.config == "batched26":
+        srcs = (graphgen.degree_spread_sources(rp, args.sources, seed=4),
+                graphgen.degree_spread_sources(rp, args.sources, seed=5))
+        result = bench_batched(args, E, G, rp, srcs, profile, torch)
+    else:
+        if args.config == "kron16":
+            sources = [int(np.flatnonzero(deg > 0)[0])]  # lowest id with degree > 0
+        else:
+            sources = graphgen.random_sources(graphgen.CSR(rp, col.array), args.sources, seed=2)
+        out = torch.empty(V, dtype=torch.int32, device="cuda")
+        result = bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen)
 
     col.free()
     w.free()

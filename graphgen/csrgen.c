@@ -153,6 +153,31 @@ static int cmp_u32(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
+/* LSD radix sort, 8-bit digits; passes whose digit is the same for every
+ * element are skipped.  Falls back to qsort when the scratch buffer cannot be
+ * allocated. */
+static void radix_u32(uint32_t *a, uint64_t n)
+{
+    uint32_t *tmp = (uint32_t *)malloc(n * sizeof(uint32_t));
+    if (!tmp) {
+        qsort(a, n, sizeof(uint32_t), cmp_u32);
+        return;
+    }
+    uint32_t *src = a, *dst = tmp;
+    for (int shift = 0; shift < 32; shift += 8) {
+        uint64_t c[257] = {0};
+        for (uint64_t i = 0; i < n; ++i) c[((src[i] >> shift) & 0xFFu) + 1]++;
+        if (c[((src[0] >> shift) & 0xFFu) + 1] == n) continue;
+        for (int d = 0; d < 256; ++d) c[d + 1] += c[d];
+        for (uint64_t i = 0; i < n; ++i) dst[c[(src[i] >> shift) & 0xFFu]++] = src[i];
+        uint32_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != a) memcpy(a, src, n * sizeof(uint32_t));
+    free(tmp);
+}
+
 static void sort_u32(uint32_t *a, uint64_t n)
 {
     if (n < 32) { /* insertion sort for short lists */
@@ -162,8 +187,10 @@ static void sort_u32(uint32_t *a, uint64_t n)
             while (j > 0 && a[j - 1] > x) { a[j] = a[j - 1]; --j; }
             a[j] = x;
         }
-    } else {
+    } else if (n < 1024) {
         qsort(a, n, sizeof(uint32_t), cmp_u32);
+    } else {
+        radix_u32(a, n);
     }
 }
 

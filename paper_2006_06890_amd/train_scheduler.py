@@ -9,7 +9,8 @@
 2. Train: the 16-64-64-6 network is trained on the GPU by the library's own
    HIP kernels (emogi_mlp_train: forward, softmax cross-entropy, backward,
    Adam), from a seeded He-uniform initialisation.
-3. Evaluate: on held-out locality-ordered power-law graphs (seeds 101-103),
+3. Evaluate: on held-out locality-ordered power-law graphs (10^8 vertices,
+   mean degree 36, exponent 2.1, runs of 1024; seeds 101-103),
    time each traversal with the fixed aligned-wave variant (the paper's
    choice), the built-in heuristic, the learned scheduler, and report the
    per-level best (sum over levels of the fastest variant's probe time).
@@ -132,6 +133,7 @@ def evaluate(E, graphgen, specs, params, torch):
                        "learned_picks": res["learned_picks"]}
                 rows.append(row)
                 log(f"eval {spec} {algo}: {row['ms']} picks {row['learned_picks']}")
+        del g, out
     return rows
 
 
@@ -139,8 +141,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="small graphs (a smoke run)")
     ap.add_argument("--epochs", type=int, default=400)
-    ap.add_argument("--eval-vertices", type=int, default=1 << 24)
+    ap.add_argument("--eval-vertices", type=int, default=100_000_000)
     ap.add_argument("--out", default=WEIGHTS, help="where to write the weights JSON")
+    ap.add_argument("--eval-only", metavar="WEIGHTS_JSON",
+                    help="skip harvesting and training: evaluate these weights and write them, "
+                         "with the new evaluation rows, to --out")
     args = ap.parse_args()
 
     sys.path.insert(0, os.path.dirname(HERE))
@@ -157,6 +162,14 @@ def main():
             train_specs += [("rmat", 16, 4, seed), ("rmat", 21, 8, seed), ("rmat", 22, 4, seed),
                             ("uniform", 20, 4, seed), ("uniform", 22, 4, seed)]
         eval_specs = [("powerlaw", args.eval_vertices, 4, s) for s in (101, 102, 103)]
+
+    if args.eval_only:
+        doc = json.load(open(args.eval_only))
+        params = np.asarray(doc["params"], dtype=np.float32)
+        doc["eval"] = evaluate(E, graphgen, eval_specs, params, torch)
+        json.dump(doc, open(args.out, "w"))
+        log(f"wrote {args.out}")
+        return
 
     X, T = harvest(E, graphgen, train_specs, torch)
     y = np.argmin(T, axis=1).astype(np.int32)

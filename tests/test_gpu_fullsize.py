@@ -1,11 +1,16 @@
-"""Parity at the benchmark's full size, in the launch configuration bench.py times.
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py times.
 
-R-MAT scale 27 (edgefactor 16, ~4.3 billion directed edges), uint64 neighbour
-ids and uint32 weights in pinned host memory read in place, heuristic
-scheduler, 256-byte request unit.  BFS levels and CC labels are compared with
-the oracle element by element; SSSP distances (Dijkstra on 4 billion edges is
-too slow for a test) are checked with the oracle's exact linear-time
-certificate, which holds iff the vector equals the true distances.
+* R-MAT scale 27 (edgefactor 16, ~4.2 billion directed edges), uint64
+  neighbour ids and uint32 weights in pinned host memory read in place,
+  heuristic scheduler, 256-byte request unit.  BFS levels and CC labels are
+  compared with the oracle element by element; SSSP distances (Dijkstra on 4
+  billion edges is too slow for a test) are checked with the oracle's exact
+  linear-time certificate, which holds iff the vector equals the true
+  distances.
+* Uniform random graph, 2^27 vertices and 2^27 x 32 samples (~8.6 billion
+  directed edges), uint32 ids and weights.  BFS levels and SSSP distances are
+  checked with the exact certificate (unit weights for BFS), CC labels element
+  by element against the oracle's union-find.
 """
 import os
 import time
@@ -19,6 +24,7 @@ import oracle
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 SCALE = int(os.environ.get("EMOGI_FULLSIZE_SCALE", "27"))
+USCALE = int(os.environ.get("EMOGI_FULLSIZE_UNIFORM_SCALE", "27"))
 
 
 def say(msg):
@@ -59,6 +65,47 @@ def test_fullsize_kron27_u64_zero_copy(gpu_device):
     assert oracle.certify_distances(rp, col.array, src, dist, w.array) == 0, "SSSP certificate failed"
     # the reachable set is the same for any positive weights
     assert np.array_equal(dist == E.INF, ref == E.INF)
+    say(f"SSSP certified ({time.time() - t:.0f}s)")
+    t = time.time()
+    ref_cc = oracle.cc(rp, col.array)
+    assert np.array_equal(lab, ref_cc), "CC labels differ from the oracle"
+    say(f"CC equal ({time.time() - t:.0f}s)")
+    col.free()
+    w.free()
+
+
+@pytest.mark.timeout(1200)
+def test_fullsize_uniform27_u32_zero_copy(gpu_device):
+    import torch
+    import paper_2006_06890_amd as E
+
+    t = time.time()
+    h = graphgen.uniform(USCALE, (1 << USCALE) * 32, seed=1)
+    V, M = h.num_vertices, h.num_edges
+    say(f"generated uniform 2^{USCALE}: V={V} E={M} in {time.time() - t:.0f}s")
+    rp = np.empty(V + 1, dtype=np.uint64)
+    col = E.PinnedArray(M, np.uint32)
+    w = E.PinnedArray(M, np.uint32)
+    h.export_into(rp.ctypes.data, col.ptr, 4, w.ptr, 3)
+    h.free()
+    src = graphgen.random_sources(graphgen.CSR(rp, col.array), 1, seed=2)[0]
+    out = torch.empty(V, dtype=torch.int32, device="cuda")
+    with E.Graph(rp, col, w, placement="host_zero_copy", symmetric=True, borrow=True) as G:
+        G.set_request_unit(256)
+        G.set_scheduler("heuristic")
+        G.bfs(src, out)
+        lv = E.to_u32(out)
+        G.sssp(src, out)
+        dist = E.to_u32(out)
+        G.cc(out)
+        lab = E.to_u32(out)
+    say("GPU traversals done; running the oracle")
+    t = time.time()
+    assert oracle.certify_distances(rp, col.array, src, lv) == 0, "BFS certificate failed"
+    say(f"BFS certified ({time.time() - t:.0f}s)")
+    t = time.time()
+    assert oracle.certify_distances(rp, col.array, src, dist, w.array) == 0, "SSSP certificate failed"
+    assert np.array_equal(dist == E.INF, lv == E.INF)
     say(f"SSSP certified ({time.time() - t:.0f}s)")
     t = time.time()
     ref_cc = oracle.cc(rp, col.array)
