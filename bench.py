@@ -190,6 +190,8 @@ def parse_args():
     ap.add_argument("--noncoherent", action="store_true", help="pin the edge arrays non-coherent")
     ap.add_argument("--no-learned", action="store_true", help="skip the scheduler comparison")
     ap.add_argument("--no-autotune", action="store_true", help="batched26: keep the default batch parameters")
+    ap.add_argument("--tier-fracs", default="0.1,0.25",
+                    help="HBM tier budgets (fractions of the edge-list bytes) run as extra arms; '' for none")
     ap.add_argument("--cpu-scale", type=int, default=None)
     ap.add_argument("--calib-bytes", type=int, default=1 << 30)
     ap.add_argument("--calibrate-only", action="store_true",
@@ -353,9 +355,28 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         result["schedulers"] = sched
         log(f"[bench] schedulers (one step, source {sources[0]}): {sched}")
 
+    arms = {}
+    fracs = [float(x) for x in args.tier_fracs.split(",") if x.strip()]
+    if fracs and not args.no_arms:
+        # HBM tier arms: the same zero-copy graph with the hub lists copied to GPU memory
+        G.set_scheduler(args.scheduler if not args.scheduler.isdigit() else "heuristic")
+        eb = args.col_bytes + 4
+        for f in fracs:
+            nv, nb = G.set_hbm_tier(int(f * M * eb))
+            r = run_step(G, sources[0], out, args.algos)
+            reached = r["bfs"]["edges_scanned"]
+            ms = sum(r[a]["total_ms"] for a in r)
+            arms[f"hbm_tier_{f:g}"] = {
+                "tier_vertices": nv, "tier_GB": round(nb / 1e9, 2),
+                "tier_edge_share": round(nb / (M * eb), 4),
+                "gteps": round(sum(M if a == "cc" else reached for a in r) / (ms * 1e6), 4),
+                **{f"{a}_ms": round(r[a]["total_ms"], 2) for a in r},
+                **{f"{a}_tier_edge_frac": round(r[a]["tier_edges"] / max(1, r[a]["edges_scanned"]), 3) for a in r},
+            }
+            log(f"[bench] arm hbm_tier_{f:g}: {arms[f'hbm_tier_{f:g}']}")
+        G.set_hbm_tier(0)
     G.close()
     if not args.no_arms:
-        arms = {}
         for placement in ("hbm", "managed"):
             try:
                 H = E.Graph(rp, col.array, w.array, placement=placement, symmetric=True)
@@ -372,6 +393,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             }
             H.close()
             log(f"[bench] arm {placement}: {arms[placement]}")
+    if arms:
         result["arms"] = arms
     return result
 

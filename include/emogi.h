@@ -93,8 +93,10 @@ typedef struct {
     uint32_t variant_hist[EMOGI_NUM_VARIANTS]; /* how many levels each variant ran     */
     uint64_t vertices_expanded;  /* frontier entries whose lists were scanned            */
     uint64_t edges_scanned;      /* sum of their out-degrees (re-expansions included)    */
-    uint64_t useful_link_bytes;  /* edges_scanned * (col_bytes + 4 if weights read)      */
+    uint64_t useful_link_bytes;  /* edges read over the host link * (col_bytes + 4 if
+                                    weights read): edges_scanned - tier_edges of them     */
     uint64_t request_bytes;      /* the same lists rounded out to the request unit R     */
+    uint64_t tier_edges;         /* of edges_scanned, those read from the HBM tier       */
     double total_ms;             /* whole traversal, HIP events on the caller's stream   */
     double expand_ms;            /* sum of the neighbour-scan kernels alone              */
     uint32_t expand_launches;    /* how many neighbour-scan kernels ran                  */
@@ -259,6 +261,21 @@ typedef struct {
 emogi_status_t emogi_autotune_batch(emogi_graph_t g, int algo, const uint64_t *srcs, uint32_t n,
                                     uint32_t *out, void *stream, emogi_batch_params_t *best,
                                     emogi_batch_trial_t *table, uint32_t table_len);
+
+/* ---- HBM tier of neighbour lists (the GPU-memory caching of graph data
+ *      that Sec. 6 proposes to cut host-link traffic further) ----
+ * Copies into GPU memory the neighbour lists (and weights) of the vertices of
+ * highest degree (ties: lower id first): the longest prefix of that order
+ * whose col_bytes (+4 with weights) bytes per edge fit in `budget_bytes`.
+ * Every scan of such a list (all variants, sampled CC, batched traversals)
+ * then reads GPU memory instead of the edge list; results are unchanged and
+ * stats.tier_edges counts the edges so read.  Replaces any previous tier;
+ * budget 0 removes it.  Synchronous (device-wide); the copy reads the lists
+ * once from the edge list's placement.  *tier_vertices and *tier_bytes (each
+ * may be NULL) receive the tier's size.  EMOGI_E_OOM_DEVICE when the tier
+ * would not leave 256 MiB of device memory free (no tier is then kept). */
+emogi_status_t emogi_set_hbm_tier(emogi_graph_t g, uint64_t budget_bytes, uint64_t *tier_vertices,
+                                  uint64_t *tier_bytes);
 
 /* Statistics of the last traversal on this handle. */
 emogi_status_t emogi_last_stats(emogi_graph_t g, emogi_stats_t *out);

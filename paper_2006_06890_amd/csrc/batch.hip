@@ -14,6 +14,7 @@
 // one hipGraph and replayed without a host round trip per level; a step whose
 // frontier is empty does nothing, so over-running the last level is harmless.
 #include "internal.h"
+#include "tier.h"
 #include "wave.h"
 
 #include <algorithm>
@@ -29,6 +30,7 @@ enum BatchCounter : int {
     B_LEVEL = 4,         // number of non-empty steps executed
     B_OVF = 5,           // SSSP: an overflowing relaxation happened / a distance overflowed
     B_EDGES = 6,         // sum of degrees of expanded vertices
+    B_TIER = 7,          // of those, edges read from the HBM tier
     B_COUNT = 8
 };
 
@@ -51,7 +53,16 @@ struct BatchArgs {
     uint64_t V;
     uint64_t align_mask;
     uint32_t hub_degree;
+    TierView tier;                     // HBM copies of hub lists (tier.bits null: none)
 };
+
+// Folds a kernel's expanded-edge counts into the batch counters.
+__device__ __forceinline__ void batch_count(const BatchArgs &a, int lane, uint64_t edges, uint64_t tedges) {
+    edges = wave_sum64(edges);
+    tedges = wave_sum64(tedges);
+    if (lane == 0 && edges) atomicAdd(&a.ctr[B_EDGES], (unsigned long long)edges);
+    if (lane == 0 && tedges) atomicAdd(&a.ctr[B_TIER], (unsigned long long)tedges);
+}
 
 // Pushes v (when `push`) to the short or hub queue by its degree.
 __device__ __forceinline__ void push_vertex(const BatchArgs &a, Stage &st, bool push, uint32_t v,
@@ -88,13 +99,17 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_short(BatchArgs a) {
     const ColT *col = static_cast<const ColT *>(a.col);
     const uint64_t n = a.ctr[B_Q0 + a.cur];
     const uint32_t level = uint32_t(a.ctr[B_LEVEL]) + 1;
-    uint64_t edges = 0;
+    uint64_t edges = 0, tedges = 0;
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t q = uint64_t(blockIdx.x) * kWavesPerBlock + wid; q < n; q += nw) {
         const uint32_t u = uniform32(a.q[q]);
         const uint64_t b = uniform64(a.row_ptr[u]), e = uniform64(a.row_ptr[u + 1]);
         const unsigned long long fm = uniform64(a.front[u]);
-        if (lane == 0) edges += e - b;
+        const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
+        if (lane == 0) {
+            edges += e - b;
+            if (src.tier) tedges += e - b;
+        }
         for (uint64_t j0 = b & ~a.align_mask; j0 < e; j0 += uint64_t(kWave) * kBUnroll) {
             uint32_t v[kBUnroll];
             bool ok[kBUnroll];
@@ -102,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_short(BatchArgs a) {
             for (int k = 0; k < kBUnroll; ++k) {
                 const uint64_t j = j0 + uint64_t(k) * kWave + lane;
                 ok[k] = j >= b && j < e;
-                v[k] = ok[k] ? uint32_t(col[j]) : 0u;
+                v[k] = ok[k] ? uint32_t(src.col[j - src.shift]) : 0u;
             }
 #pragma unroll
             for (int k = 0; k < kBUnroll; ++k) {
@@ -112,8 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_short(BatchArgs a) {
         }
     }
     finish_queue(st, a.nq, &a.ctr[B_Q0 + (a.cur ^ 1)], lane, wid);
-    edges = wave_sum64(edges);
-    if (lane == 0 && edges) atomicAdd(&a.ctr[B_EDGES], (unsigned long long)edges);
+    batch_count(a, lane, edges, tedges);
 }
 
 template <class ColT>
@@ -124,12 +138,16 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_hub(BatchArgs a) {
     const ColT *col = static_cast<const ColT *>(a.col);
     const uint64_t n = a.ctr[B_H0 + a.cur];
     const uint32_t level = uint32_t(a.ctr[B_LEVEL]) + 1;
-    uint64_t edges = 0;
+    uint64_t edges = 0, tedges = 0;
     for (uint64_t q = blockIdx.x; q < n; q += gridDim.x) {
         const uint32_t u = uniform32(a.h[q]);
         const uint64_t b = uniform64(a.row_ptr[u]), e = uniform64(a.row_ptr[u + 1]);
         const unsigned long long fm = uniform64(a.front[u]);
-        if (lane == 0 && wid == 0) edges += e - b;
+        const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
+        if (lane == 0 && wid == 0) {
+            edges += e - b;
+            if (src.tier) tedges += e - b;
+        }
         for (uint64_t j0 = b & ~a.align_mask; j0 < e; j0 += uint64_t(kBlock) * 2) {
             uint32_t v[2];
             bool ok[2];
@@ -137,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_hub(BatchArgs a) {
             for (int k = 0; k < 2; ++k) {
                 const uint64_t j = j0 + uint64_t(k) * kBlock + uint64_t(wid) * kWave + lane;
                 ok[k] = j >= b && j < e;
-                v[k] = ok[k] ? uint32_t(col[j]) : 0u;
+                v[k] = ok[k] ? uint32_t(src.col[j - src.shift]) : 0u;
             }
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
@@ -147,8 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_hub(BatchArgs a) {
         }
     }
     finish_queue(st, a.nq, &a.ctr[B_Q0 + (a.cur ^ 1)], lane, wid);
-    edges = wave_sum64(edges);
-    if (lane == 0 && edges) atomicAdd(&a.ctr[B_EDGES], (unsigned long long)edges);
+    batch_count(a, lane, edges, tedges);
 }
 
 // SSSP: lane s of the wave is source s.  The wave loads 64 (neighbour,
@@ -215,25 +232,28 @@ __global__ __launch_bounds__(kBlock) void k_bsssp_short(BatchArgs a) {
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(a.col);
     const uint64_t n = a.ctr[B_Q0 + a.cur];
-    uint64_t edges = 0;
+    uint64_t edges = 0, tedges = 0;
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t q = uint64_t(blockIdx.x) * kWavesPerBlock + wid; q < n; q += nw) {
         const uint32_t u = uniform32(a.q[q]);
         const uint64_t b = uniform64(a.row_ptr[u]), e = uniform64(a.row_ptr[u + 1]);
         const unsigned long long fm = uniform64(a.front[u]);
         const uint32_t du = a.out[uint64_t(u) * 64 + lane];
-        if (lane == 0) edges += e - b;
+        const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
+        if (lane == 0) {
+            edges += e - b;
+            if (src.tier) tedges += e - b;
+        }
         for (uint64_t j0 = b & ~a.align_mask; j0 < e; j0 += kWave) {
             const uint64_t j = j0 + lane;
             const bool ok = j >= b && j < e;
-            const uint32_t vl = ok ? uint32_t(col[j]) : 0u;
-            const uint32_t wl = ok ? a.w[j] : 0u;
+            const uint32_t vl = ok ? uint32_t(src.col[j - src.shift]) : 0u;
+            const uint32_t wl = ok ? src.w[j - src.shift] : 0u;
             sssp_relax_chunk(a, st, lane, fm, du, vl, wl, ok);
         }
     }
     finish_queue(st, a.nq, &a.ctr[B_Q0 + (a.cur ^ 1)], lane, wid);
-    edges = wave_sum64(edges);
-    if (lane == 0 && edges) atomicAdd(&a.ctr[B_EDGES], (unsigned long long)edges);
+    batch_count(a, lane, edges, tedges);
 }
 
 template <class ColT>
@@ -243,24 +263,27 @@ __global__ __launch_bounds__(kBlock) void k_bsssp_hub(BatchArgs a) {
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(a.col);
     const uint64_t n = a.ctr[B_H0 + a.cur];
-    uint64_t edges = 0;
+    uint64_t edges = 0, tedges = 0;
     for (uint64_t q = blockIdx.x; q < n; q += gridDim.x) {
         const uint32_t u = uniform32(a.h[q]);
         const uint64_t b = uniform64(a.row_ptr[u]), e = uniform64(a.row_ptr[u + 1]);
         const unsigned long long fm = uniform64(a.front[u]);
         const uint32_t du = a.out[uint64_t(u) * 64 + lane];
-        if (lane == 0 && wid == 0) edges += e - b;
+        const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
+        if (lane == 0 && wid == 0) {
+            edges += e - b;
+            if (src.tier) tedges += e - b;
+        }
         for (uint64_t j0 = (b & ~a.align_mask) + uint64_t(wid) * kWave; j0 < e; j0 += kBlock) {
             const uint64_t j = j0 + lane;
             const bool ok = j >= b && j < e;
-            const uint32_t vl = ok ? uint32_t(col[j]) : 0u;
-            const uint32_t wl = ok ? a.w[j] : 0u;
+            const uint32_t vl = ok ? uint32_t(src.col[j - src.shift]) : 0u;
+            const uint32_t wl = ok ? src.w[j - src.shift] : 0u;
             sssp_relax_chunk(a, st, lane, fm, du, vl, wl, ok);
         }
     }
     finish_queue(st, a.nq, &a.ctr[B_Q0 + (a.cur ^ 1)], lane, wid);
-    edges = wave_sum64(edges);
-    if (lane == 0 && edges) atomicAdd(&a.ctr[B_EDGES], (unsigned long long)edges);
+    batch_count(a, lane, edges, tedges);
 }
 
 // Clears the masks of the vertices just expanded (they become the next
@@ -447,6 +470,7 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
     a.n = n;
     a.V = V;
     a.align_mask = std::max<uint32_t>(1, g->request_unit / g->col_bytes) - 1;
+    a.tier = tier_view(g);
     a.hub_degree = P.hub_degree;
     // ---- init ----
     EMOGI_HIP_TRY(hipMemcpyAsync(b.srcs, srcs, n * sizeof(uint64_t), hipMemcpyHostToDevice, s), EMOGI_E_HIP);
@@ -560,7 +584,8 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
     memset(&S, 0, sizeof(S));
     S.iterations = uint32_t(levels);
     S.edges_scanned = edges;
-    S.useful_link_bytes = edges * (g->col_bytes + (sssp ? 4u : 0u));
+    S.tier_edges = b.host_ctr[B_TIER];
+    S.useful_link_bytes = (edges - S.tier_edges) * (g->col_bytes + (sssp ? 4u : 0u));
     S.total_ms = ms;
     S.expand_ms = ms;
     S.expand_launches = uint32_t(steps);

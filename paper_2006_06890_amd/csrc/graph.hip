@@ -136,6 +136,7 @@ static void release(emogi_graph_s *g) {
                     (void *)p.snap_midbits})
         if (x) (void)hipFree(x);
     if (g->mlp_params) (void)hipFree(g->mlp_params);
+    tier_release(g);
     BatchPool &b = g->batch;
     for (int i = 0; i < 2; ++i) {
         if (b.mask[i]) (void)hipFree(b.mask[i]);

@@ -34,7 +34,22 @@ enum Counter : int {
     C_FAR = 5,       // SSSP: entries appended to the far pile
     C_FARMIN = 6,    // SSSP: smallest live distance in the far pile
     C_MID = 7,       // SSSP: entries appended to the mid pile
-    C_COUNT = 8
+    C_CHOICE = 8,    // scheduler: variant picked for the next frontier (low 32 bits)
+    C_FEAT = 9,      // scheduler: the next frontier's 16 features (fp32, 8 slots)
+    C_TIER = 17,     // edges of expanded vertices whose lists were read from the HBM tier
+    C_COUNT = 18
+};
+
+// HBM tier of neighbour lists (device arrays; see tier.h).
+struct Tier {
+    uint32_t *bits = nullptr;   // V bits
+    uint32_t *ids = nullptr;    // tier vertices, ascending
+    uint64_t *start = nullptr;  // n + 1 offsets into col / w
+    void *col = nullptr;
+    uint32_t *w = nullptr;
+    uint32_t n = 0;
+    uint64_t elems = 0;         // list elements held
+    uint64_t bytes = 0;         // device bytes of col + w
 };
 
 struct Pool {
@@ -100,8 +115,13 @@ struct emogi_graph_s {
 
     emogi::Pool pool;
     emogi::BatchPool batch;
+    emogi::Tier tier;
     emogi_batch_params_t batch_params{1024, 4, 8, 1};
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;
     emogi_stats_t stats{};
 };
+
+namespace emogi {
+void tier_release(emogi_graph_s *g);  // frees the HBM tier (tier.hip)
+}  // namespace emogi

@@ -22,10 +22,14 @@ constexpr int kNParams = kNH * kNIn + kNH + kNH * kNH + kNH + kNOut * kNH + kNOu
 constexpr int kHistBins = 8;
 
 // acc[0..7]: degree histogram of the frontier, acc[8]: sum of degrees.
-__global__ __launch_bounds__(256) void k_frontier_hist(const uint32_t *queue, uint32_t n,
+// The frontier length is n, or *n_dev when n_dev is set (a frontier the
+// previous level has just written, whose length the host does not know yet).
+__global__ __launch_bounds__(256) void k_frontier_hist(const uint32_t *queue, uint64_t n,
+                                                       const unsigned long long *n_dev,
                                                        const uint64_t *row_ptr,
                                                        unsigned long long *acc) {
     __shared__ unsigned long long s_acc[kHistBins + 1];
+    if (n_dev) n = *n_dev;
     if (threadIdx.x < kHistBins + 1) s_acc[threadIdx.x] = 0;
     __syncthreads();
     unsigned long long local[kHistBins + 1] = {};
@@ -49,11 +53,14 @@ struct FeatureConsts {
 };
 
 // One wave: features from the histogram, then z = W3 relu(W2 relu(W1 x + b1) + b2) + b3,
-// argmax into *choice.  Also stores the features for harvesting.
-__global__ __launch_bounds__(64) void k_mlp_pick(const unsigned long long *acc, FeatureConsts c,
-                                                 const float *params, int *choice, float *feat_out) {
+// argmax into *choice (-1 without weights).  Also stores the features for
+// harvesting, and clears the histogram for its next use.  n_dev as above.
+__global__ __launch_bounds__(64) void k_mlp_pick(unsigned long long *acc, FeatureConsts c,
+                                                 const unsigned long long *n_dev, const float *params,
+                                                 int *choice, float *feat_out) {
     __shared__ float x[kNIn], h1[kNH], h2[kNH], z[kNOut];
     const int t = threadIdx.x;
+    if (n_dev) c.n = float(*n_dev);
     if (t == 0) {
         const float sumdeg = float(acc[kHistBins]);
         x[0] = log2f(1.f + c.n) / 32.f;
@@ -67,7 +74,9 @@ __global__ __launch_bounds__(64) void k_mlp_pick(const unsigned long long *acc, 
         x[15] = c.managed;
     }
     __syncthreads();
+    if (t < kHistBins + 1) acc[t] = 0;
     if (t < kNIn && feat_out) feat_out[t] = x[t];
+    if (!params && t == 0) *choice = -1;
     const float *W1 = params, *b1 = W1 + kNH * kNIn, *W2 = b1 + kNH, *b2 = W2 + kNH * kNH,
                 *W3 = b2 + kNH, *b3 = W3 + kNOut * kNH;
     if (params) {
@@ -121,14 +130,7 @@ static emogi_status_t sched_scratch(emogi_graph_s *g, SchedScratch *s) {
 
 // Frontier features (and the MLP's pick when weights are loaded).
 // Returns the variant, or -1 on a HIP failure.
-static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue,
-                        hipStream_t stream, float *features_host) {
-    SchedScratch s;
-    if (sched_scratch(g, &s) != EMOGI_OK) return -1;
-    if (hipMemsetAsync(s.acc, 0, 128, stream) != hipSuccess) return -1;
-    const unsigned grid = unsigned(std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 1024)));
-    hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, uint32_t(n),
-                       g->row_ptr, s.acc);
+static FeatureConsts feature_consts(const emogi_graph_s *g, int algo, uint64_t n) {
     FeatureConsts c;
     c.n = float(n);
     c.V = float(g->V);
@@ -137,8 +139,19 @@ static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *
     c.weights = algo == 1 ? 1.f : 0.f;
     c.zero_copy = g->placement == EMOGI_PLACE_HOST_ZERO_COPY ? 1.f : 0.f;
     c.managed = g->placement == EMOGI_PLACE_MANAGED ? 1.f : 0.f;
-    hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(64), 0, stream, s.acc, c, g->mlp_params, s.choice,
-                       s.feat);
+    return c;
+}
+
+static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue,
+                        hipStream_t stream, float *features_host) {
+    SchedScratch s;
+    if (sched_scratch(g, &s) != EMOGI_OK) return -1;
+    if (hipMemsetAsync(s.acc, 0, 128, stream) != hipSuccess) return -1;
+    const unsigned grid = unsigned(std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 1024)));
+    hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, n,
+                       static_cast<const unsigned long long *>(nullptr), g->row_ptr, s.acc);
+    hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(64), 0, stream, s.acc, feature_consts(g, algo, n),
+                       static_cast<const unsigned long long *>(nullptr), g->mlp_params, s.choice, s.feat);
     struct {
         int choice;
         float feat[kNIn];
@@ -152,6 +165,52 @@ static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *
     if (features_host) memcpy(features_host, h.feat, sizeof(h.feat));
     if (!g->mlp_params || h.choice < 0 || h.choice >= kNOut) return heuristic_variant(g, n);
     return h.choice;
+}
+
+// Whether the scheduler needs the frontier's features at all.
+bool sched_needs_features(const emogi_graph_s *g) {
+    return g->record_features || (g->sched_mode == EMOGI_SCHED_LEARNED && g->mlp_params);
+}
+
+// Clears the histogram before a traversal that uses sched_prefetch.
+emogi_status_t sched_begin(emogi_graph_s *g, hipStream_t stream) {
+    SchedScratch s;
+    emogi_status_t st = sched_scratch(g, &s);
+    if (st != EMOGI_OK) return st;
+    EMOGI_HIP_TRY(hipMemsetAsync(s.acc, 0, 128, stream), EMOGI_E_HIP);
+    return EMOGI_OK;
+}
+
+// Features and pick for the frontier a level has just written (its length is
+// counters[C_NEXT] on the device), enqueued behind that level: the results
+// land in the counter block the level copies back anyway, so the choice costs
+// no extra host round trip.  The histogram is left cleared by k_mlp_pick.
+emogi_status_t sched_prefetch(emogi_graph_s *g, int algo, const uint32_t *queue, unsigned long long *counters,
+                              hipStream_t stream) {
+    SchedScratch s;
+    emogi_status_t st = sched_scratch(g, &s);
+    if (st != EMOGI_OK) return st;
+    const unsigned grid = unsigned(std::max<uint64_t>(1, std::min<uint64_t>((g->V + 255) / 256, 1024)));
+    hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, uint64_t(0),
+                       static_cast<const unsigned long long *>(&counters[C_NEXT]), g->row_ptr, s.acc);
+    hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(64), 0, stream, s.acc, feature_consts(g, algo, 0),
+                       static_cast<const unsigned long long *>(&counters[C_NEXT]), g->mlp_params,
+                       reinterpret_cast<int *>(&counters[C_CHOICE]), reinterpret_cast<float *>(&counters[C_FEAT]));
+    EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+    return EMOGI_OK;
+}
+
+// Variant for a frontier whose pick and features sched_prefetch computed
+// (hc: the host copy of the counter block).  Same rule as choose_variant.
+int choose_prefetched(const emogi_graph_s *g, uint64_t n, const unsigned long long *hc, float *features) {
+    if (features) memcpy(features, &hc[C_FEAT], kNIn * sizeof(float));
+    const int m = g->sched_mode;
+    if (m >= 0 && m < EMOGI_NUM_VARIANTS) return m;
+    if (m == EMOGI_SCHED_LEARNED && g->mlp_params) {
+        const int c = int(uint32_t(hc[C_CHOICE] & 0xFFFFFFFFull));
+        if (c >= 0 && c < kNOut) return c;
+    }
+    return heuristic_variant(g, n);
 }
 
 // Variant for the level; fills `features` (16 floats) when non-null.

@@ -20,6 +20,7 @@
 //  * vertex state (levels, distances, labels, visited bitmap, stamps) stays
 //    in HBM; only the edge list (and weights) cross the host link.
 #include "internal.h"
+#include "tier.h"
 #include "wave.h"
 
 #include <algorithm>
@@ -38,17 +39,25 @@ constexpr int kMaxGrid = 256 * 8; // 8 blocks of 4 waves on each of the 256 CUs
 // End of a scan block: flush the staged frontier and fold the statistics.
 __device__ __forceinline__ void finish_block(Stage &st, uint32_t *next, unsigned long long *ctr,
                                              int lane, int wid, uint64_t edges, uint64_t reqb,
-                                             uint64_t verts) {
+                                             uint64_t verts, uint64_t tedges) {
     finish_queue(st, next, &ctr[C_NEXT], lane, wid);
     edges = wave_sum64(edges);
     reqb = wave_sum64(reqb);
     verts = wave_sum64(verts);
+    tedges = wave_sum64(tedges);
     if (lane == 0) {
         if (edges) atomicAdd(&ctr[C_EDGES], (unsigned long long)edges);
         if (reqb) atomicAdd(&ctr[C_REQBYTES], (unsigned long long)reqb);
         if (verts) atomicAdd(&ctr[C_VERTS], (unsigned long long)verts);
+        if (tedges) atomicAdd(&ctr[C_TIER], (unsigned long long)tedges);
     }
 }
+
+// Per-list statistics: every expanded list counts its edges; a list read over
+// the host link also counts its request-granular bytes, a tier list its edges.
+__device__ __forceinline__ void count_list(bool tier, uint64_t b, uint64_t e, uint32_t cb, uint32_t R,
+                                           uint64_t &edges, uint64_t &reqb, uint64_t &verts,
+                                           uint64_t &tedges);
 
 // ---------------------------------------------------------------------------
 // Application step per neighbour (Algorithm 1's workload + condition).
@@ -180,11 +189,21 @@ struct ScanArgs {
     uint32_t req_unit;      // bytes
     uint32_t col_bytes;
     const uint64_t *chunk_scan;  // V5 only
+    TierView tier;               // HBM copies of hub lists (tier.bits null: none)
 };
 
 __device__ __forceinline__ uint64_t request_bytes(uint64_t s, uint64_t e, uint32_t cb, uint32_t R) {
     uint64_t first = (s * cb) / R, last = (e * cb + R - 1) / R;
     return (last - first) * R;
+}
+
+__device__ __forceinline__ void count_list(bool tier, uint64_t b, uint64_t e, uint32_t cb, uint32_t R,
+                                           uint64_t &edges, uint64_t &reqb, uint64_t &verts,
+                                           uint64_t &tedges) {
+    edges += e - b;
+    verts += 1;
+    if (tier) tedges += e - b;
+    else reqb += request_bytes(b, e, cb, R);
 }
 
 __device__ __forceinline__ uint32_t frontier_at(const ScanArgs &s, uint32_t q) {
@@ -201,18 +220,15 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s, OpArgs a) {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(s.col);
-    uint64_t edges = 0, reqb = 0, verts = 0;
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t q = uint64_t(blockIdx.x) * kWavesPerBlock + wid; q < s.n; q += nw) {
         const uint32_t u = uniform32(frontier_at(s, uint32_t(q)));
         const uint64_t b = uniform64(s.row_ptr[u]), e = uniform64(s.row_ptr[u + 1]);
         if (b == e) continue;
         const uint32_t uval = uniform32(source_value<A>(a, u));
-        if (lane == 0) {
-            edges += e - b;
-            reqb += request_bytes(b, e, s.col_bytes, s.req_unit);
-            verts += 1;
-        }
+        const ListSrc<ColT> src = list_src(s.tier, col, s.w, u, b);
+        if (lane == 0) count_list(src.tier, b, e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
         const uint64_t start = ALIGN ? (b & ~s.align_mask) : b;
         for (uint64_t j0 = start; j0 < e; j0 += uint64_t(kWave) * kUnroll) {
             uint32_t v[kUnroll], w[kUnroll];
@@ -224,8 +240,8 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s, OpArgs a) {
                 v[k] = 0;
                 w[k] = 0;
                 if (ok[k]) {
-                    v[k] = load_col(col, j);
-                    if (A == A_SSSP) w[k] = s.w[j];
+                    v[k] = load_col(src.col, j - src.shift);
+                    if (A == A_SSSP) w[k] = src.w[j - src.shift];
                 }
             }
 #pragma unroll
@@ -235,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s, OpArgs a) {
             }
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts);
+    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges);
 }
 
 // ---------------------------------------------------------------------------
@@ -247,17 +263,14 @@ __global__ __launch_bounds__(kBlock) void k_block(ScanArgs s, OpArgs a) {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(s.col);
-    uint64_t edges = 0, reqb = 0, verts = 0;
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
     for (uint64_t q = blockIdx.x; q < s.n; q += gridDim.x) {
         const uint32_t u = uniform32(frontier_at(s, uint32_t(q)));
         const uint64_t b = uniform64(s.row_ptr[u]), e = uniform64(s.row_ptr[u + 1]);
         if (b == e) continue;
         const uint32_t uval = uniform32(source_value<A>(a, u));
-        if (lane == 0 && wid == 0) {
-            edges += e - b;
-            reqb += request_bytes(b, e, s.col_bytes, s.req_unit);
-            verts += 1;
-        }
+        const ListSrc<ColT> src = list_src(s.tier, col, s.w, u, b);
+        if (lane == 0 && wid == 0) count_list(src.tier, b, e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
         const uint64_t start = b & ~s.align_mask;
         for (uint64_t j0 = start; j0 < e; j0 += uint64_t(kBlock) * 2) {
             uint32_t v[2], w[2];
@@ -269,8 +282,8 @@ __global__ __launch_bounds__(kBlock) void k_block(ScanArgs s, OpArgs a) {
                 v[k] = 0;
                 w[k] = 0;
                 if (ok[k]) {
-                    v[k] = load_col(col, j);
-                    if (A == A_SSSP) w[k] = s.w[j];
+                    v[k] = load_col(src.col, j - src.shift);
+                    if (A == A_SSSP) w[k] = src.w[j - src.shift];
                 }
             }
 #pragma unroll
@@ -280,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_block(ScanArgs s, OpArgs a) {
             }
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts);
+    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_group(ScanArgs s, OpArgs a) {
     const ColT *col = static_cast<const ColT *>(s.col);
     constexpr int kGroups = kWave / G;
     const int g = lane / G, gl = lane % G;
-    uint64_t edges = 0, reqb = 0, verts = 0;
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t q0 = (uint64_t(blockIdx.x) * kWavesPerBlock + wid) * kGroups; q0 < s.n;
          q0 += nw * kGroups) {
@@ -310,26 +323,26 @@ __global__ __launch_bounds__(kBlock) void k_group(ScanArgs s, OpArgs a) {
             e = s.row_ptr[u + 1];
         }
         uint32_t uval = 0;
-        if (has && b < e) uval = source_value<A>(a, u);
-        if (gl == 0 && b < e) {
-            edges += e - b;
-            reqb += request_bytes(b, e, s.col_bytes, s.req_unit);
-            verts += 1;
+        ListSrc<ColT> src{col, s.w, 0, false};
+        if (has && b < e) {
+            uval = source_value<A>(a, u);
+            src = list_src(s.tier, col, s.w, u, b);
         }
+        if (gl == 0 && b < e) count_list(src.tier, b, e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
         // G == 1: no rounding (thread walks its own list); G == 16: round to the group span.
         const uint64_t start = (G == 1) ? b : (b & ~uint64_t(G - 1));
         for (uint64_t j = start + gl; __ballot(j < e) != 0; j += G) {
             const bool ok = (j >= b) && (j < e);
             uint32_t v = 0, w = 0;
             if (ok) {
-                v = load_col(col, j);
-                if (A == A_SSSP) w = s.w[j];
+                v = load_col(src.col, j - src.shift);
+                if (A == A_SSSP) w = src.w[j - src.shift];
             }
             const int r = ok ? visit<A>(a, uval, v, w) : 0;
             emit<A>(st, r, v, s.next, a, lane);
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts);
+    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s, OpArgs a) {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(s.col);
-    uint64_t edges = 0, reqb = 0, verts = 0;
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
     const uint64_t total = s.chunk_scan[s.n];
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t k0 = (uint64_t(blockIdx.x) * kWavesPerBlock + wid) * kChunksPerWave; k0 < total;
@@ -372,6 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s, OpArgs a) {
         uint32_t u = uniform32(frontier_at(s, q));
         uint64_t b = uniform64(s.row_ptr[u]), e = uniform64(s.row_ptr[u + 1]);
         uint32_t uval = uniform32(source_value<A>(a, u));
+        ListSrc<ColT> src = list_src(s.tier, col, s.w, u, b);
         for (uint64_t kb = k0; kb < kend; kb += kUnroll) {
             uint32_t v[kUnroll], w[kUnroll], uv[kUnroll];
             bool ok[kUnroll];
@@ -392,19 +406,17 @@ __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s, OpArgs a) {
                             b = uniform64(s.row_ptr[u]);
                             e = uniform64(s.row_ptr[u + 1]);
                             uval = uniform32(source_value<A>(a, u));
+                            src = list_src(s.tier, col, s.w, u, b);
                         }
                     }
                     uv[i] = uval;
-                    if (kk == qfirst && lane == 0) {
-                        edges += e - b;
-                        reqb += request_bytes(b, e, s.col_bytes, s.req_unit);
-                        verts += 1;
-                    }
+                    if (kk == qfirst && lane == 0)
+                        count_list(src.tier, b, e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
                     const uint64_t j = (b & ~s.align_mask) + (kk - qfirst) * kWave + lane;
                     ok[i] = (j >= b) && (j < e);
                     if (ok[i]) {
-                        v[i] = load_col(col, j);
-                        if (A == A_SSSP) w[i] = s.w[j];
+                        v[i] = load_col(src.col, j - src.shift);
+                        if (A == A_SSSP) w[i] = src.w[j - src.shift];
                     }
                 }
             }
@@ -415,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s, OpArgs a) {
             }
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts);
+    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges);
 }
 
 // ---- V5 prefix scan of per-entry chunk counts (reduce, scan partials, scan) ----
@@ -637,20 +649,25 @@ constexpr int kCcProbe = 1024;
 
 template <class ColT>
 __global__ __launch_bounds__(kBlock) void k_cc_sample(const uint64_t *row_ptr, const ColT *col, uint64_t V,
-                                                      uint32_t *parent, unsigned long long *ctr) {
-    uint64_t edges = 0;
+                                                      TierView tier, uint32_t *parent, unsigned long long *ctr) {
+    uint64_t edges = 0, tedges = 0;
     for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
          v += uint64_t(gridDim.x) * blockDim.x) {
         const uint64_t b = row_ptr[v], e = row_ptr[v + 1];
         const uint64_t n = e - b < kCcSample ? e - b : kCcSample;
+        if (n == 0) continue;
+        const ListSrc<ColT> src = list_src(tier, col, static_cast<const uint32_t *>(nullptr), uint32_t(v), b);
         ColT nb[kCcSample];
-        for (uint64_t r = 0; r < n; ++r) nb[r] = col[b + r];
+        for (uint64_t r = 0; r < n; ++r) nb[r] = src.col[b + r - src.shift];
         for (uint64_t r = 0; r < n; ++r)
             if (uint64_t(nb[r]) < V) uf_link(parent, uint32_t(v), uint32_t(nb[r]));
         edges += n;
+        if (src.tier) tedges += n;
     }
     edges = wave_sum64(edges);
+    tedges = wave_sum64(tedges);
     if (lane_id() == 0 && edges) atomicAdd(&ctr[C_EDGES], (unsigned long long)edges);
+    if (lane_id() == 0 && tedges) atomicAdd(&ctr[C_TIER], (unsigned long long)tedges);
 }
 
 __global__ void k_compress(uint32_t *parent, uint64_t V) {
@@ -814,6 +831,11 @@ int heuristic_variant(const emogi_graph_s *g, uint64_t n) {
 
 int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue, hipStream_t stream,
                    float *features);
+bool sched_needs_features(const emogi_graph_s *g);
+emogi_status_t sched_begin(emogi_graph_s *g, hipStream_t stream);
+emogi_status_t sched_prefetch(emogi_graph_s *g, int algo, const uint32_t *queue, unsigned long long *counters,
+                              hipStream_t stream);
+int choose_prefetched(const emogi_graph_s *g, uint64_t n, const unsigned long long *hc, float *features);
 
 // Probe mode: save (restore=false) or restore (restore=true) the state a
 // level step modifies, so every variant can be timed on the same level.
@@ -904,10 +926,10 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                           EMOGI_E_HIP);
             if (g->col_bytes == 8)
                 hipLaunchKernelGGL(k_cc_sample<uint64_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, g->row_ptr,
-                                   static_cast<const uint64_t *>(g->col), V, out, p.counters);
+                                   static_cast<const uint64_t *>(g->col), V, tier_view(g), out, p.counters);
             else
                 hipLaunchKernelGGL(k_cc_sample<uint32_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, g->row_ptr,
-                                   static_cast<const uint32_t *>(g->col), V, out, p.counters);
+                                   static_cast<const uint32_t *>(g->col), V, tier_view(g), out, p.counters);
             hipLaunchKernelGGL(k_compress, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
             hipLaunchKernelGGL(k_cc_probe, dim3((kCcProbe + 255) / 256), dim3(256), 0, stream, out, V,
                                p.cc_probe);
@@ -920,6 +942,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                           EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
             S.edges_scanned += p.host_counters[C_EDGES];
+            S.tier_edges += p.host_counters[C_TIER];
             std::sort(roots.begin(), roots.end());
             uint32_t big = roots[0], best = 0;
             for (size_t i = 0, j; i < roots.size(); i = j) {
@@ -1023,8 +1046,15 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
         return EMOGI_OK;
     };
+    // The scheduler's features and pick for the next frontier are computed
+    // behind each level and come back with its counters (have_pick); a
+    // frontier cut from an SSSP pile, or the first one, is scored on its own.
+    const bool prefetch = V > 0 && sched_needs_features(g);
+    bool have_pick = false;
+    if (prefetch && (st = sched_begin(g, stream)) != EMOGI_OK) return st;
     while (n > 0 || mid_n > 0 || far_n > 0) {
         if (n == 0) {
+            have_pick = false;
             // near frontier exhausted: refill the mid pile from the far pile if
             // needed, then cut the mid pile at (live minimum + delta)
             unsigned long long m;
@@ -1073,6 +1103,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             s.req_unit = g->request_unit;
             s.col_bytes = g->col_bytes;
             s.chunk_scan = nullptr;
+            s.tier = tier_view(g);
             OpArgs a;
             a.state = out;
             a.bitmap = p.bitmap;
@@ -1123,6 +1154,10 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                                    p.block_sums, nbw, s.next, p.counters);
                 EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             }
+            if (prefetch) {
+                emogi_status_t e3 = sched_prefetch(g, algo, s.next, p.counters, stream);
+                if (e3 != EMOGI_OK) return e3;
+            }
             EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
                                          hipMemcpyDeviceToHost, stream),
                           EMOGI_E_HIP);
@@ -1132,7 +1167,8 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         };
         float feats[16];
         const bool want_feats = g->record_features && iter < EMOGI_MAX_LEVEL_STATS;
-        int var = choose_variant(g, algo, n, queue, stream, want_feats ? feats : nullptr);
+        int var = have_pick ? choose_prefetched(g, n, p.host_counters, want_feats ? feats : nullptr)
+                            : choose_variant(g, algo, n, queue, stream, want_feats ? feats : nullptr);
         if (var < 0) {
             set_error("scheduler kernels failed");
             return EMOGI_E_HIP;
@@ -1156,6 +1192,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         }
         float ms = 0.f;
         if ((st = run_level(var, &ms)) != EMOGI_OK) return st;
+        have_pick = prefetch;
         const unsigned long long *hc = p.host_counters;
         if (iter < EMOGI_MAX_LEVEL_STATS) {
             S.level_variant[iter] = uint8_t(var);
@@ -1168,6 +1205,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         S.expand_ms += ms;
         S.expand_launches += 1;
         S.edges_scanned += hc[C_EDGES];
+        S.tier_edges += hc[C_TIER];
         S.request_bytes += hc[C_REQBYTES];
         S.vertices_expanded += hc[C_VERTS];
         if (hc[C_OVERFLOW]) overflow_seen = true;
@@ -1185,7 +1223,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     if (kalgo == A_LINK)
         hipLaunchKernelGGL(k_compress, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
     S.iterations = iter;
-    S.useful_link_bytes = S.edges_scanned * (g->col_bytes + (algo == A_SSSP ? 4u : 0u));
+    S.useful_link_bytes = (S.edges_scanned - S.tier_edges) * (g->col_bytes + (algo == A_SSSP ? 4u : 0u));
     if (overflow_seen) {
         EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
                       EMOGI_E_HIP);

@@ -41,6 +41,7 @@ class Stats(ctypes.Structure):
         ("edges_scanned", ctypes.c_uint64),
         ("useful_link_bytes", ctypes.c_uint64),
         ("request_bytes", ctypes.c_uint64),
+        ("tier_edges", ctypes.c_uint64),
         ("total_ms", ctypes.c_double),
         ("expand_ms", ctypes.c_double),
         ("expand_launches", ctypes.c_uint32),
@@ -63,6 +64,7 @@ class Stats(ctypes.Structure):
             "edges_scanned": self.edges_scanned,
             "useful_link_bytes": self.useful_link_bytes,
             "request_bytes": self.request_bytes,
+            "tier_edges": self.tier_edges,
             "total_ms": self.total_ms,
             "expand_ms": self.expand_ms,
             "expand_launches": self.expand_launches,
@@ -187,6 +189,7 @@ def lib():
             "emogi_set_scheduler": (i32, [p, i32]),
             "emogi_set_sssp_delta": (i32, [p, u32]),
             "emogi_set_cc_algorithm": (i32, [p, i32]),
+            "emogi_set_hbm_tier": (i32, [p, u64, p, p]),
             "emogi_set_frontier_order": (i32, [p, i32]),
             "emogi_set_scheduler_weights": (i32, [p, p, sz]),
             "emogi_bfs": (i32, [p, u64, p, p]),
@@ -332,6 +335,13 @@ class Graph:
         """'label_propagation' or 'sampled_union_find' (default)."""
         check(lib().emogi_set_cc_algorithm(
             self._h, {"label_propagation": 0, "sampled_union_find": 1}[name]))
+
+    def set_hbm_tier(self, budget_bytes):
+        """Copies the highest-degree vertices' lists that fit in budget_bytes
+        into GPU memory (0 removes the tier); returns (vertices, bytes) held."""
+        nv, nb = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        check(lib().emogi_set_hbm_tier(self._h, int(budget_bytes), ctypes.byref(nv), ctypes.byref(nb)))
+        return int(nv.value), int(nb.value)
 
     def set_sssp_delta(self, delta):
         """SSSP near-far band width (0 = plain label correcting)."""

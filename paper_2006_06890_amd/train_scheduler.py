@@ -119,7 +119,7 @@ def evaluate(E, graphgen, specs, params, torch):
                         scan += st["expand_ms"]
                         total += st["total_ms"]
                         if mode == "probe":
-                            best += float(np.sum(np.min(np.array(st["level_probe_ms"]), axis=1)))
+                            best += float(np.sum(np.min(np.array(st["level_probe_ms"]).reshape(-1, 6), axis=1)))
                         if mode == "learned":
                             picks += st["level_variant"]
                     # scan-kernel time (what the choice affects); end-to-end beside it

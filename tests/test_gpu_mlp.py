@@ -110,6 +110,24 @@ def test_learned_picks_match_oracle_network(gpu_device):
             if algo == "bfs":
                 assert F[0][1] == pytest.approx(1.0 / g.num_vertices)
                 assert F[0][12] == 0.0 and F[0][14] == 1.0
+                # every BFS level's frontier is the set of vertices at that
+                # level: its size, degree sum and degree histogram fix the
+                # features the scheduler saw
+                lv = E.to_u32(out)
+                deg = g.degrees().astype(np.int64)
+                edges = [0, 2, 4, 8, 16, 64, 256, 4096, np.iinfo(np.int64).max]
+                assert len(st["level_frontier"]) == F.shape[0]
+                for i in range(F.shape[0]):
+                    d = deg[lv == i]
+                    n = d.shape[0]
+                    assert st["level_frontier"][i] == n
+                    exp_f = np.zeros(12)
+                    exp_f[0] = np.log2(1 + n) / 32
+                    exp_f[1] = n / g.num_vertices
+                    exp_f[2] = np.log2(1 + d.sum()) / 40
+                    exp_f[3] = d.sum() / g.num_edges
+                    exp_f[4:12] = np.histogram(d, bins=edges)[0] / n
+                    np.testing.assert_allclose(F[i][:12], exp_f, rtol=1e-5, atol=1e-7, err_msg=f"level {i}")
         exp = oracle.cc(g.row_ptr, g.col)
         np.testing.assert_array_equal(E.to_u32(out), exp)
 
