@@ -190,6 +190,8 @@ def parse_args():
     ap.add_argument("--noncoherent", action="store_true", help="pin the edge arrays non-coherent")
     ap.add_argument("--no-learned", action="store_true", help="skip the scheduler comparison")
     ap.add_argument("--no-autotune", action="store_true", help="batched26: keep the default batch parameters")
+    ap.add_argument("--pagerank-iters", type=int, default=3,
+                    help="PageRank iterations run once after the timed region (0: skip)")
     ap.add_argument("--tier-fracs", default="0.1,0.25",
                     help="HBM tier budgets (fractions of the edge-list bytes) run as extra arms; '' for none")
     ap.add_argument("--cpu-scale", type=int, default=None)
@@ -354,6 +356,22 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             sched[name]["step_ms"] = round(sum(r[a]["total_ms"] for a in r), 2)
         result["schedulers"] = sched
         log(f"[bench] schedulers (one step, source {sources[0]}): {sched}")
+
+    if args.pagerank_iters > 0 and "cc" in args.algos:
+        # PageRank (the paper's fourth workload): every iteration streams all lists
+        pr = torch.empty(V, dtype=torch.int64, device="cuda")
+        G.pagerank(args.pagerank_iters, out=pr)
+        st = G.stats()
+        it_ms = st["expand_ms"] / max(1, st["iterations"])
+        result["pagerank"] = {
+            "iterations": st["iterations"], "fixed_point_bits": 40, "damping": 0.85,
+            "ms_per_iteration": round(st["total_ms"] / max(1, st["iterations"]), 2),
+            "scan_ms_per_iteration": round(it_ms, 2),
+            "gteps": round(M / (st["total_ms"] / max(1, st["iterations"]) * 1e6), 3),
+            "link_GBps": round(st["useful_link_bytes"] / max(1, st["iterations"]) / (it_ms * 1e6), 2),
+        }
+        del pr
+        log(f"[bench] pagerank: {result['pagerank']}")
 
     arms = {}
     fracs = [float(x) for x in args.tier_fracs.split(",") if x.strip()]

@@ -162,24 +162,36 @@ emogi_status_t emogi_graph_destroy(emogi_graph_t g);
  * host link at its copy rate when read at random. */
 emogi_status_t emogi_set_request_unit(emogi_graph_t g, uint32_t bytes);
 emogi_status_t emogi_set_scheduler(emogi_graph_t g, int mode);
-/* SSSP distance band (near-far worklist): an improved vertex whose new
- * distance is below the current split joins the next frontier, otherwise it
- * waits in a far pile; when the near frontier empties the split moves to the
- * smallest waiting distance + delta.  0 disables the bands (every improved
- * vertex re-enters at once).  Default 4.  Results are identical for any
- * value; only the amount of re-expansion changes. */
+/* BFS levels enqueued per host wait.  Each level's kernels read the frontier
+ * length the previous level left in device memory, so a batch needs no host
+ * round trip between its levels (Sec. 4.2 launches one kernel per level and
+ * the host checks for termination after each).  1: one level per wait, the
+ * variant chosen per level; k > 1 (<= 64): k levels per wait with one
+ * variant (the fixed one, else the heuristic's pick for the whole graph) and
+ * pushes through the LDS-staged queue; 0 (default): 8 on graphs of up to
+ * 2^22 vertices, 1 above.  Always 1 when the scheduler records features,
+ * runs the network or probes.  Results are identical. */
+emogi_status_t emogi_set_level_batch(emogi_graph_t g, uint32_t levels);
+/* SSSP distance band (near-far worklist): every vertex whose distance
+ * improves is marked; a round expands, in ascending id order, the marked
+ * vertices whose distance is below the current split, and when none is left
+ * the split moves to the smallest marked distance + delta.  0 disables the
+ * bands (every improved vertex is expanded in the next round).  Default 4.
+ * Results are identical for any value; only the amount of re-expansion
+ * changes. */
 emogi_status_t emogi_set_sssp_delta(emogi_graph_t g, uint32_t delta);
+/* Frontier order for BFS and CC label propagation: 0 appends pushes through
+ * per-wave LDS segments (order unspecified); 1 (default) collects the next
+ * frontier as a bitmap and lists it in ascending vertex id, so each level
+ * reads neighbour lists in edge-array order.  SSSP always lists its marks.
+ * Results are identical either way. */
+emogi_status_t emogi_set_frontier_order(emogi_graph_t g, int ordered);
 /* CC algorithm (both give every vertex the smallest id of its component):
  * EMOGI_CC_LABEL_PROPAGATION: all vertices start active and push their label
  *   over every list until nothing changes (the paper's workload, Sec. 5.4);
  * EMOGI_CC_SAMPLED_UNION_FIND (default): hook each vertex to its first two
  *   neighbours, compress, then read whole lists only for vertices outside
  *   the largest tree found (Afforest-style; far fewer list bytes). */
-/* Frontier order: 0 appends pushes through per-wave LDS segments (order
- * unspecified); 1 (default) collects the next frontier as a bitmap and lists
- * it in ascending vertex id, so each level reads neighbour lists in
- * edge-array order.  Results are identical either way. */
-emogi_status_t emogi_set_frontier_order(emogi_graph_t g, int ordered);
 #define EMOGI_CC_LABEL_PROPAGATION 0
 #define EMOGI_CC_SAMPLED_UNION_FIND 1
 emogi_status_t emogi_set_cc_algorithm(emogi_graph_t g, int algorithm);
@@ -228,6 +240,24 @@ emogi_status_t emogi_mlp_train(const float *X, const int32_t *y, uint32_t N,
 emogi_status_t emogi_bfs(emogi_graph_t g, uint64_t src, uint32_t *levels, void *stream);
 emogi_status_t emogi_sssp(emogi_graph_t g, uint64_t src, uint32_t *dist, void *stream);
 emogi_status_t emogi_cc(emogi_graph_t g, uint32_t *labels, void *stream);
+
+/* PageRank (the fourth workload of Sec. 5.1), pull form on an undirected
+ * graph (created with EMOGI_F_SYMMETRIC, else EMOGI_E_NOT_SYMMETRIC), in
+ * fixed point so that every sum is exact: scores are uint64 with
+ * `frac_bits` fractional bits (one = 2^frac_bits, 1 <= frac_bits <= 62) and
+ * the damping factor is the integer damping_fixed = floor(damping * one),
+ * which must be below one.  With deg(u) the list length of u:
+ *   pr_0(v)     = floor(one / V)
+ *   c(u)        = floor(pr(u) / deg(u))   (0 when deg(u) = 0)
+ *   pr_{t+1}(v) = floor((one - damping_fixed) / V)
+ *                 + floor(damping_fixed * sum over neighbours u of c(u) / one)
+ * A vertex without neighbours passes nothing on.  Integer sums make the
+ * result independent of the order of additions.  Runs `iters` iterations,
+ * each streaming every neighbour list once (V5 chunks of all lists, the HBM
+ * tier when set).  `scores`: device uint64[V], written with pr_iters.
+ * Returns after the last iteration; stats count one level per iteration. */
+emogi_status_t emogi_pagerank(emogi_graph_t g, uint32_t iters, uint32_t frac_bits, uint64_t damping_fixed,
+                              uint64_t *scores, void *stream);
 
 /* ---- batched multi-source traversal (the paper runs 64 sources per graph,
  *      Sec. 5.2; here up to 64 run together and each list read from host

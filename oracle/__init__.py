@@ -14,6 +14,8 @@ Contents
   computations for tiny graphs.
 * ``certify_distances``, ``certify_cc``: linear-time certificates used where a
   full run is too slow.
+* ``pagerank``: the power iteration of PageRank (EMOGI's fourth workload,
+  Sec. 5.1) in fixed point, so every sum is exact.
 * ``request_bytes``: host-link bytes of a request-granular scan (Sec. 3.3,
   Sec. 4.3.2), ``reached_edges``: the TEPS numerator.
 * ``mlp``: fp64 reference of the per-level scheduler network.
@@ -65,6 +67,7 @@ def _load():
             "oracle_certify_cc": (i32, [u64, p, p, i32, p]),
             "oracle_request_bytes": (u64, [u64, p, i32, u64, p]),
             "oracle_reached_edges": (u64, [u64, p, p]),
+            "oracle_pagerank": (i32, [u64, p, p, i32, ctypes.c_uint32, u64, ctypes.c_uint32, p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -137,6 +140,18 @@ def cc(row_ptr, col):
     rc = _load().oracle_cc(V, _ptr(rp), _ptr(c), cb, _ptr(out))
     if rc:
         raise OracleError(f"oracle_cc failed ({rc})")
+    return out
+
+
+def pagerank(row_ptr, col, frac_bits, damping_fixed, iters):
+    """Fixed-point PageRank after ``iters`` iterations (oracle_pagerank):
+    uint64 scores with ``frac_bits`` fractional bits, damping factor
+    ``damping_fixed`` / 2^frac_bits."""
+    V, rp, c, cb = _csr(row_ptr, col)
+    out = np.empty(V, dtype=np.uint64)
+    rc = _load().oracle_pagerank(V, _ptr(rp), _ptr(c), cb, frac_bits, damping_fixed, iters, _ptr(out))
+    if rc:
+        raise OracleError(f"oracle_pagerank failed ({rc})")
     return out
 
 

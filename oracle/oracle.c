@@ -14,6 +14,7 @@
  *                  (Sec. 5.1 systems compared; Sec. 5.2 integer weights).
  *   - CC label   : smallest vertex id in the vertex's connected component of
  *                  the undirected graph (Sec. 5.4: CC on undirected graphs).
+ *   - PageRank   : the power iteration in fixed point (see oracle_pagerank).
  * Unreachable is 0xFFFFFFFF for levels and distances.
  *
  * CSR (Sec. 2.1, Fig. 1): row_ptr[V+1] (uint64), col[E] of 4 or 8 bytes,
@@ -390,4 +391,46 @@ uint64_t oracle_reached_edges(uint64_t V, const uint64_t *row_ptr,
     for (uint64_t v = 0; v < V; ++v)
         if (d[v] != ORC_INF32) total += row_ptr[v + 1] - row_ptr[v];
     return total;
+}
+
+/* ------------------------------------------------------------------ */
+/* PageRank (EMOGI's fourth workload, Sec. 5.1 and Sec. 5.4), pull     */
+/* form on an undirected graph, in fixed point so that every sum is   */
+/* exact and the result cannot depend on the order of additions.      */
+/* With one = 2^F and d the damping factor scaled to an integer        */
+/* (d < one):                                                          */
+/*   pr_0(v)     = floor(one / V)                                     */
+/*   c_t(u)      = floor(pr_t(u) / deg(u))   (0 when deg(u) = 0)       */
+/*   s_t(v)      = sum of c_t(u) over the neighbours u of v            */
+/*   pr_{t+1}(v) = floor((one - d) / V) + floor(d * s_t(v) / one)      */
+/* A vertex without neighbours passes no score on (no redistribution). */
+/* Scores stay below one, so d * s fits in 128 bits.                   */
+/* ------------------------------------------------------------------ */
+int oracle_pagerank(uint64_t V, const uint64_t *row_ptr, const void *col,
+                    int col_bytes, uint32_t frac_bits, uint64_t d,
+                    uint32_t iters, uint64_t *pr)
+{
+    if (frac_bits < 1 || frac_bits > 62) return -1;
+    const uint64_t one = (uint64_t)1 << frac_bits;
+    if (d >= one) return -1;
+    if (V == 0) return 0;
+    uint64_t *c = (uint64_t *)malloc(V * sizeof(uint64_t));
+    if (!c) return -2;
+    const uint64_t base = (one - d) / V;
+    for (uint64_t v = 0; v < V; ++v) pr[v] = one / V;
+    for (uint32_t t = 0; t < iters; ++t) {
+        for (uint64_t u = 0; u < V; ++u) {
+            uint64_t deg = row_ptr[u + 1] - row_ptr[u];
+            c[u] = deg ? pr[u] / deg : 0;
+        }
+        for (uint64_t v = 0; v < V; ++v) {
+            uint64_t s = 0;
+            for (uint64_t i = row_ptr[v]; i < row_ptr[v + 1]; ++i)
+                s += c[col_at(col, col_bytes, i)];
+            unsigned __int128 prod = (unsigned __int128)d * s;
+            pr[v] = base + (uint64_t)(prod >> frac_bits);
+        }
+    }
+    free(c);
+    return 0;
 }

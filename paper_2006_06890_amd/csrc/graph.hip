@@ -128,12 +128,14 @@ static void release(emogi_graph_s *g) {
     if (p.block_sums) (void)hipFree(p.block_sums);
     if (p.counters) (void)hipFree(p.counters);
     if (p.host_counters) (void)hipHostFree(p.host_counters);
+    if (p.pr_acc) (void)hipFree(p.pr_acc);
+    if (p.pr_contrib) (void)hipFree(p.pr_contrib);
+    if (p.level_ctr) (void)hipFree(p.level_ctr);
+    if (p.level_host) (void)hipHostFree(p.level_host);
     if (p.features) (void)hipFree(p.features);
     if (p.degree_hist) (void)hipFree(p.degree_hist);
-    for (void *x : {(void *)p.snap_state, (void *)p.snap_stamp, (void *)p.snap_bitmap, (void *)p.far[0],
-                    (void *)p.far[1], (void *)p.farbits, (void *)p.snap_farbits, (void *)p.cc_probe,
-                    (void *)p.nextbits, (void *)p.mid[0], (void *)p.mid[1], (void *)p.midbits,
-                    (void *)p.snap_midbits})
+    for (void *x : {(void *)p.snap_state, (void *)p.snap_stamp, (void *)p.snap_bitmap, (void *)p.snap_nextbits,
+                    (void *)p.cc_probe, (void *)p.nextbits})
         if (x) (void)hipFree(x);
     if (g->mlp_params) (void)hipFree(g->mlp_params);
     tier_release(g);
@@ -370,6 +372,15 @@ emogi_status_t emogi_set_cc_algorithm(emogi_graph_t g, int algorithm) {
         return EMOGI_E_INVALID;
     }
     g->cc_sampled = algorithm == EMOGI_CC_SAMPLED_UNION_FIND;
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_set_level_batch(emogi_graph_t g, uint32_t levels) {
+    if (!g || levels > 64) {
+        set_error("level batch must be 0 (automatic) .. 64");
+        return EMOGI_E_INVALID;
+    }
+    g->level_batch = levels;
     return EMOGI_OK;
 }
 

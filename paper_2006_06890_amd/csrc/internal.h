@@ -31,13 +31,11 @@ enum Counter : int {
     C_REQBYTES = 2,  // request-granular link bytes of those lists
     C_OVERFLOW = 3,  // SSSP: some relaxation exceeded 0xFFFFFFFE
     C_VERTS = 4,     // expanded vertices
-    C_FAR = 5,       // SSSP: entries appended to the far pile
-    C_FARMIN = 6,    // SSSP: smallest live distance in the far pile
-    C_MID = 7,       // SSSP: entries appended to the mid pile
-    C_CHOICE = 8,    // scheduler: variant picked for the next frontier (low 32 bits)
-    C_FEAT = 9,      // scheduler: the next frontier's 16 features (fp32, 8 slots)
-    C_TIER = 17,     // edges of expanded vertices whose lists were read from the HBM tier
-    C_COUNT = 18
+    C_BANDMIN = 5,   // SSSP: 2^32 - (smallest distance of a marked vertex left for a later band), 0: none
+    C_CHOICE = 6,    // scheduler: variant picked for the next frontier (low 32 bits)
+    C_FEAT = 7,      // scheduler: the next frontier's 16 features (fp32, 8 slots)
+    C_TIER = 15,     // edges of expanded vertices whose lists were read from the HBM tier
+    C_COUNT = 16
 };
 
 // HBM tier of neighbour lists (device arrays; see tier.h).
@@ -55,7 +53,7 @@ struct Tier {
 struct Pool {
     uint32_t *queue[2] = {nullptr, nullptr}; // frontier ids, V entries each
     uint32_t *bitmap = nullptr;               // BFS visited / SSSP overflow marks
-    uint32_t *stamp = nullptr;                // SSSP/CC: round in which v was last pushed
+    uint32_t *stamp = nullptr;                // CC label propagation: round in which v was last pushed
     uint64_t *chunk_scan = nullptr;           // V5: exclusive scan of per-entry chunk counts
     uint64_t *block_sums = nullptr;           // V5: scan partials
     unsigned long long *counters = nullptr;   // C_COUNT device counters
@@ -65,14 +63,14 @@ struct Pool {
     uint32_t *snap_state = nullptr;           // probe mode: saved state of a level
     uint32_t *snap_stamp = nullptr;
     uint32_t *snap_bitmap = nullptr;
-    uint32_t *far[2] = {nullptr, nullptr};    // SSSP near-far: far piles (V entries each)
-    uint32_t *farbits = nullptr;              // SSSP near-far: in-far-pile bit per vertex
-    uint32_t *snap_farbits = nullptr;
-    uint32_t *mid[2] = {nullptr, nullptr};    // SSSP near-far: mid piles (V entries each)
-    uint32_t *midbits = nullptr;              // SSSP near-far: in-mid-pile bit per vertex
-    uint32_t *snap_midbits = nullptr;
+    uint32_t *snap_nextbits = nullptr;        // probe mode: saved SSSP marks
     uint32_t *cc_probe = nullptr;             // CC: roots of probed vertices
-    uint32_t *nextbits = nullptr;             // ordered frontier bitmap
+    uint32_t *nextbits = nullptr;             // ordered frontier bitmap (SSSP: improved, not yet expanded)
+    unsigned long long *pr_acc = nullptr;     // PageRank: per-vertex sums of the iteration
+    uint64_t *pr_contrib = nullptr;           // PageRank: floor(score / degree) per vertex
+    unsigned long long *level_ctr = nullptr;  // BFS level batches: one counter block per level
+    unsigned long long *level_host = nullptr; // pinned mirror
+    uint32_t level_cap = 0;
     size_t chunk_cap = 0;
 };
 
@@ -108,6 +106,7 @@ struct emogi_graph_s {
     uint32_t sssp_delta = 4;       // near-far band width; 0 = plain label correcting
     bool cc_sampled = true;        // CC by sampled union-find (else min-label propagation)
     bool ordered_frontier = true;  // list each next frontier in ascending id order
+    uint32_t level_batch = 0;      // BFS levels per host wait (0: automatic)
     int sched_mode = EMOGI_SCHED_HEURISTIC;
     bool record_features = false;  // store per-level frontier features in the stats
     float *mlp_params = nullptr;   // device, 5638 floats, or null

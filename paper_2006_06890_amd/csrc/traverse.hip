@@ -65,16 +65,11 @@ __device__ __forceinline__ void count_list(bool tier, uint64_t b, uint64_t e, ui
 struct OpArgs {
     uint32_t *state;    // levels / dist / labels (the caller's output array)
     uint32_t *bitmap;   // BFS visited bits; SSSP overflow marks
-    uint32_t *stamp;    // SSSP/CC: last round in which v was pushed
-    uint32_t tag;       // BFS: level of the next frontier; SSSP/CC: round number
+    uint32_t *stamp;    // CC label propagation: last round in which v was pushed
+    uint32_t tag;       // BFS: level of the next frontier; CC: round number
     uint32_t V;         // neighbour ids at or above V are ignored (malformed input)
-    uint32_t split;     // SSSP near-far: improvements at or above it go to the far pile
-    uint32_t *far;      // SSSP: far pile (append at ctr[C_FAR])
-    uint32_t *farbits;  // SSSP: one bit per vertex already in the far pile
-    uint32_t mid_limit; // SSSP: improvements in [split, mid_limit) go to the mid pile
-    uint32_t *mid;      // SSSP: mid pile (append at ctr[C_MID])
-    uint32_t *midbits;  // SSSP: one bit per vertex already in the mid pile
-    uint32_t *nextbits; // ordered frontier: next frontier as a bitmap (null: LDS-staged queue)
+    uint32_t *nextbits; // ordered frontier: next frontier as a bitmap (null: LDS-staged queue);
+                        // SSSP: vertices improved and not yet expanded
     unsigned long long *ctr;
 };
 
@@ -106,7 +101,7 @@ __device__ __forceinline__ void uf_link(uint32_t *parent, uint32_t a, uint32_t b
     }
 }
 
-// Returns 1 when v joins the next frontier, 2 when it joins the SSSP far pile, else 0.
+// Returns 1 when v joins the next frontier (SSSP: when its distance improved), else 0.
 template <int A>
 __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v, uint32_t w) {
     if (v >= a.V) return 0;
@@ -119,7 +114,8 @@ __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v,
         a.state[v] = a.tag;
         return 1;
     } else if (A == A_SSSP) {
-        // SSSP: relax the edge; an improved vertex is re-activated once per round.
+        // SSSP: relax the edge; an improved vertex is marked, and the listing
+        // pass after the round decides in which band it is expanded.
         uint64_t nd = uint64_t(uval) + w;
         if (nd > 0xFFFFFFFEull) {
             atomicOr(&a.bitmap[v >> 5], 1u << (v & 31u));
@@ -128,15 +124,7 @@ __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v,
         }
         if (a.state[v] <= uint32_t(nd)) return 0;
         uint32_t old = atomicMin(&a.state[v], uint32_t(nd));
-        if (old <= uint32_t(nd)) return 0;
-        if (uint32_t(nd) >= a.split) {
-            // beyond the current band: park it once in the mid pile (the next
-            // few bands) or, further out, in the far pile
-            const uint32_t bit = 1u << (v & 31u);
-            if (uint32_t(nd) < a.mid_limit) return (atomicOr(&a.midbits[v >> 5], bit) & bit) ? 0 : 3;
-            return (atomicOr(&a.farbits[v >> 5], bit) & bit) ? 0 : 2;
-        }
-        return atomicExch(&a.stamp[v], a.tag) != a.tag ? 1 : 0;
+        return old > uint32_t(nd) ? 1 : 0;
     } else if (A == A_LINK) {
         uf_link(a.state, uval, v);
         return 0;
@@ -149,38 +137,25 @@ __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v,
     }
 }
 
-// Hands a visit result to the next-frontier staging (1) or the far pile (2).
+// Hands a visit result to the next-frontier staging.
 // Uniform: every lane of the wave calls it.
 template <int A>
 __device__ __forceinline__ void emit(Stage &st, int r, uint32_t v, uint32_t *next, const OpArgs &a,
                                      int lane) {
     if (a.nextbits) {
-        // ordered frontier: mark; a compaction pass later lists the marks in id order
-        if (r == 1) atomicOr(&a.nextbits[v >> 5], 1u << (v & 31u));
+        // ordered frontier: mark; a listing pass later lists the marks in id order
+        const uint32_t bit = 1u << (v & 31u);
+        if (r == 1 && !(a.nextbits[v >> 5] & bit)) atomicOr(&a.nextbits[v >> 5], bit);
     } else {
         stage(st, r == 1, v, next, &a.ctr[C_NEXT], lane);
-    }
-    if (A == A_SSSP) {
-        const uint64_t m = __ballot(r == 2);
-        if (m) {
-            uint32_t base = 0;
-            if (lane == 0) base = uint32_t(atomicAdd(&a.ctr[C_FAR], (unsigned long long)__popcll(m)));
-            base = __shfl(base, 0);
-            if (r == 2) a.far[base + rank_below(m)] = v;
-        }
-        const uint64_t mm = __ballot(r == 3);
-        if (mm) {
-            uint32_t base = 0;
-            if (lane == 0) base = uint32_t(atomicAdd(&a.ctr[C_MID], (unsigned long long)__popcll(mm)));
-            base = __shfl(base, 0);
-            if (r == 3) a.mid[base + rank_below(mm)] = v;
-        }
     }
 }
 
 struct ScanArgs {
     const uint32_t *queue;  // null: the frontier is every vertex 0..n-1
     uint32_t n;
+    const unsigned long long *n_dev;  // when set, the frontier length is *n_dev (left on
+                                      // the device by the previous level) instead of n
     const uint64_t *row_ptr;
     const void *col;
     const uint32_t *w;
@@ -210,12 +185,20 @@ __device__ __forceinline__ uint32_t frontier_at(const ScanArgs &s, uint32_t q) {
     return s.queue ? s.queue[q] : q;
 }
 
+// The kernel's view of the scan arguments with the frontier length resolved.
+__device__ __forceinline__ ScanArgs resolved(const ScanArgs &s0) {
+    ScanArgs s = s0;
+    if (s0.n_dev) s.n = uint32_t(*s0.n_dev);
+    return s;
+}
+
 // ---------------------------------------------------------------------------
 // V2/V3: one wave per frontier vertex.  V3 rounds the start down to the
 // request unit and masks the lanes below the true start (Sec. 4.3.2).
 // ---------------------------------------------------------------------------
 template <class ColT, int A, bool ALIGN>
-__global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s, OpArgs a) {
+__global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s0, OpArgs a) {
+    const ScanArgs s = resolved(s0);
     __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
@@ -258,7 +241,8 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s, OpArgs a) {
 // V4: one 256-thread workgroup per frontier vertex (for hub lists).
 // ---------------------------------------------------------------------------
 template <class ColT, int A>
-__global__ __launch_bounds__(kBlock) void k_block(ScanArgs s, OpArgs a) {
+__global__ __launch_bounds__(kBlock) void k_block(ScanArgs s0, OpArgs a) {
+    const ScanArgs s = resolved(s0);
     __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
@@ -302,7 +286,8 @@ __global__ __launch_bounds__(kBlock) void k_block(ScanArgs s, OpArgs a) {
 // The wave loops until no lane of it has work, so staging stays uniform.
 // ---------------------------------------------------------------------------
 template <class ColT, int A, int G>
-__global__ __launch_bounds__(kBlock) void k_group(ScanArgs s, OpArgs a) {
+__global__ __launch_bounds__(kBlock) void k_group(ScanArgs s0, OpArgs a) {
+    const ScanArgs s = resolved(s0);
     __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
@@ -368,66 +353,185 @@ __device__ __forceinline__ uint32_t find_entry(const uint64_t *scan, uint32_t n,
     return lo;
 }
 
+// The chunks one wave owns: runs of kChunksPerWave consecutive chunks, one
+// run per grid stride.  All fields are wave-uniform.
+template <class ColT>
+struct ChunkCursor {
+    uint64_t run0, kb, kend;           // current run [run0, kend), next chunk kb
+    uint64_t stride, total;            // run stride of the grid, chunks of the level
+    uint32_t q;                        // frontier entry owning chunk kb (or an earlier one)
+    uint64_t qfirst, qnext;            // its chunk range
+    uint32_t u, uval;
+    uint64_t b, e;
+    ListSrc<ColT> src;
+};
+
+// kUnroll chunks' neighbours (and weights), loaded, not yet visited.
+struct ChunkGroup {
+    uint32_t v[kUnroll], w[kUnroll], uv[kUnroll];
+    bool ok[kUnroll];
+};
+
 template <class ColT, int A>
-__global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s, OpArgs a) {
-    __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
-    const int lane = lane_id(), wid = threadIdx.x / kWave;
-    Stage st{seg[wid], 0};
-    const ColT *col = static_cast<const ColT *>(s.col);
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
-    const uint64_t total = s.chunk_scan[s.n];
-    const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
-    for (uint64_t k0 = (uint64_t(blockIdx.x) * kWavesPerBlock + wid) * kChunksPerWave; k0 < total;
-         k0 += nw * kChunksPerWave) {
-        const uint64_t kend = k0 + kChunksPerWave < total ? k0 + kChunksPerWave : total;
-        uint32_t q = uniform32(find_entry(s.chunk_scan, s.n, k0));
-        uint64_t qfirst = uniform64(s.chunk_scan[q]), qnext = uniform64(s.chunk_scan[q + 1]);
-        uint32_t u = uniform32(frontier_at(s, q));
-        uint64_t b = uniform64(s.row_ptr[u]), e = uniform64(s.row_ptr[u + 1]);
-        uint32_t uval = uniform32(source_value<A>(a, u));
-        ListSrc<ColT> src = list_src(s.tier, col, s.w, u, b);
-        for (uint64_t kb = k0; kb < kend; kb += kUnroll) {
-            uint32_t v[kUnroll], w[kUnroll], uv[kUnroll];
-            bool ok[kUnroll];
+__device__ __forceinline__ void enter_entry(ChunkCursor<ColT> &c, const ScanArgs &s, const OpArgs &a) {
+    c.u = uniform32(frontier_at(s, c.q));
+    c.b = uniform64(s.row_ptr[c.u]);
+    c.e = uniform64(s.row_ptr[c.u + 1]);
+    c.uval = uniform32(source_value<A>(a, c.u));
+    c.src = list_src(s.tier, static_cast<const ColT *>(s.col), s.w, c.u, c.b);
+}
+
+template <class ColT, int A>
+__device__ __forceinline__ void open_run(ChunkCursor<ColT> &c, const ScanArgs &s, const OpArgs &a, uint64_t k0) {
+    if (k0 >= c.total) {
+        c.kb = c.kend = c.total;
+        return;
+    }
+    c.run0 = c.kb = k0;
+    c.kend = k0 + kChunksPerWave < c.total ? k0 + kChunksPerWave : c.total;
+    c.q = uniform32(find_entry(s.chunk_scan, s.n, k0));
+    c.qfirst = uniform64(s.chunk_scan[c.q]);
+    c.qnext = uniform64(s.chunk_scan[c.q + 1]);
+    enter_entry<ColT, A>(c, s, a);
+}
+
+// Issues the loads of the next kUnroll chunks (those left in the run) and
+// moves the cursor past them, to the next run when this one is done.
+template <class ColT, int A>
+__device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, const ScanArgs &s, const OpArgs &a,
+                                           int lane, uint64_t &edges, uint64_t &reqb, uint64_t &verts,
+                                           uint64_t &tedges) {
 #pragma unroll
-            for (int i = 0; i < kUnroll; ++i) {
-                const uint64_t kk = kb + i;
-                ok[i] = false;
-                v[i] = 0;
-                w[i] = 0;
-                uv[i] = uval;
-                if (kk < kend) {
-                    while (kk >= qnext) {  // next entry that owns chunks (uniform)
-                        ++q;
-                        qfirst = qnext;
-                        qnext = uniform64(s.chunk_scan[q + 1]);
-                        if (qnext > qfirst) {
-                            u = uniform32(frontier_at(s, q));
-                            b = uniform64(s.row_ptr[u]);
-                            e = uniform64(s.row_ptr[u + 1]);
-                            uval = uniform32(source_value<A>(a, u));
-                            src = list_src(s.tier, col, s.w, u, b);
-                        }
-                    }
-                    uv[i] = uval;
-                    if (kk == qfirst && lane == 0)
-                        count_list(src.tier, b, e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
-                    const uint64_t j = (b & ~s.align_mask) + (kk - qfirst) * kWave + lane;
-                    ok[i] = (j >= b) && (j < e);
-                    if (ok[i]) {
-                        v[i] = load_col(src.col, j - src.shift);
-                        if (A == A_SSSP) w[i] = src.w[j - src.shift];
-                    }
-                }
+    for (int i = 0; i < kUnroll; ++i) {
+        const uint64_t kk = c.kb + i;
+        g.ok[i] = false;
+        g.v[i] = 0;
+        g.w[i] = 0;
+        g.uv[i] = c.uval;
+        if (kk < c.kend) {
+            while (kk >= c.qnext) {  // next entry that owns chunks (uniform)
+                ++c.q;
+                c.qfirst = c.qnext;
+                c.qnext = uniform64(s.chunk_scan[c.q + 1]);
+                if (c.qnext > c.qfirst) enter_entry<ColT, A>(c, s, a);
             }
-#pragma unroll
-            for (int i = 0; i < kUnroll; ++i) {
-                const int r = ok[i] ? visit<A>(a, uv[i], v[i], w[i]) : 0;
-                emit<A>(st, r, v[i], s.next, a, lane);
+            g.uv[i] = c.uval;
+            if (kk == c.qfirst && lane == 0)
+                count_list(c.src.tier, c.b, c.e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
+            const uint64_t j = (c.b & ~s.align_mask) + (kk - c.qfirst) * kWave + lane;
+            g.ok[i] = (j >= c.b) && (j < c.e);
+            if (g.ok[i]) {
+                g.v[i] = load_col(c.src.col, j - c.src.shift);
+                if (A == A_SSSP) g.w[i] = c.src.w[j - c.src.shift];
             }
         }
     }
+    c.kb += kUnroll;
+    if (c.kb >= c.kend) open_run<ColT, A>(c, s, a, c.run0 + c.stride);
+}
+
+// V5 main loop, software-pipelined: the loads of the next chunk group are in
+// flight while the current group's neighbours are visited, so a wave keeps
+// host-link reads outstanding through its HBM-side work.
+template <class ColT, int A>
+__global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s0, OpArgs a) {
+    const ScanArgs s = resolved(s0);
+    __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    Stage st{seg[wid], 0};
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
+    ChunkCursor<ColT> c;
+    c.total = s.chunk_scan[s.n];
+    c.stride = uint64_t(gridDim.x) * kWavesPerBlock * kChunksPerWave;
+    open_run<ColT, A>(c, s, a, (uint64_t(blockIdx.x) * kWavesPerBlock + wid) * kChunksPerWave);
+    bool live = c.kb < c.kend;
+    ChunkGroup cur;
+    if (live) load_group<ColT, A>(c, cur, s, a, lane, edges, reqb, verts, tedges);
+    while (live) {
+        const bool more = c.kb < c.kend;
+        ChunkGroup nxt;
+        if (more) load_group<ColT, A>(c, nxt, s, a, lane, edges, reqb, verts, tedges);
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) {
+            const int r = cur.ok[i] ? visit<A>(a, cur.uv[i], cur.v[i], cur.w[i]) : 0;
+            emit<A>(st, r, cur.v[i], s.next, a, lane);
+        }
+        if (more) cur = nxt;
+        live = more;
+    }
     finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges);
+}
+
+// ---------------------------------------------------------------------------
+// PageRank (the fourth EMOGI workload, Sec. 5.1): every iteration streams
+// all neighbour lists, like CC's first round.  Pull form on an undirected
+// graph in fixed point (emogi_pagerank): the chunks of vertex u's list are
+// dealt out as in V5; each wave sums the contributions c of a chunk's
+// neighbours and adds the chunk's sum to acc[u].  The sums are integers, so
+// the result does not depend on the order in which chunks finish.
+// ---------------------------------------------------------------------------
+struct PrArgs {
+    const uint64_t *contrib;  // c(v) = floor(pr(v) / deg(v)) of the current iteration
+    unsigned long long *acc;  // per-vertex sums for the next iteration (zero on entry)
+    unsigned long long *ctr;  // C_EDGES, C_REQBYTES, C_VERTS, C_TIER
+};
+
+template <class ColT>
+__global__ __launch_bounds__(kBlock) void k_pr_pull(ScanArgs s, PrArgs pa) {
+    const int lane = lane_id();
+    OpArgs a{};  // the cursor reads only source_value<A_LINK>, which is the vertex id
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
+    ChunkCursor<ColT> c;
+    c.total = s.chunk_scan[s.n];
+    c.stride = uint64_t(gridDim.x) * kWavesPerBlock * kChunksPerWave;
+    open_run<ColT, A_LINK>(c, s, a, (uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * kChunksPerWave);
+    while (c.kb < c.kend) {
+        ChunkGroup g;
+        load_group<ColT, A_LINK>(c, g, s, a, lane, edges, reqb, verts, tedges);
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) {
+            const uint64_t x = (g.ok[i] && g.v[i] < s.n) ? pa.contrib[g.v[i]] : 0ull;
+            const uint64_t sum = wave_sum64(x);
+            if (lane == 0 && sum) atomicAdd(&pa.acc[g.uv[i]], (unsigned long long)sum);
+        }
+    }
+    edges = wave_sum64(edges);
+    reqb = wave_sum64(reqb);
+    verts = wave_sum64(verts);
+    tedges = wave_sum64(tedges);
+    if (lane == 0) {
+        if (edges) atomicAdd(&pa.ctr[C_EDGES], (unsigned long long)edges);
+        if (reqb) atomicAdd(&pa.ctr[C_REQBYTES], (unsigned long long)reqb);
+        if (verts) atomicAdd(&pa.ctr[C_VERTS], (unsigned long long)verts);
+        if (tedges) atomicAdd(&pa.ctr[C_TIER], (unsigned long long)tedges);
+    }
+}
+
+// pr(v) = base + floor(d * acc(v) / 2^F); acc(v) = 0; c(v) = floor(pr(v) / deg(v)).
+__global__ void k_pr_finish(const uint64_t *row_ptr, uint64_t V, uint64_t base, uint64_t d, uint32_t F,
+                            unsigned long long *acc, uint64_t *pr, uint64_t *contrib) {
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
+         v += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t sum = acc[v];
+        acc[v] = 0;
+        const uint64_t lo = d * sum, hi = __umul64hi(d, sum);
+        const uint64_t x = base + ((hi << (64 - F)) | (lo >> F));
+        pr[v] = x;
+        const uint64_t deg = row_ptr[v + 1] - row_ptr[v];
+        contrib[v] = deg ? x / deg : 0;
+    }
+}
+
+// pr(v) = floor(2^F / V), c(v) = floor(pr(v) / deg(v)), acc(v) = 0.
+__global__ void k_pr_init(const uint64_t *row_ptr, uint64_t V, uint64_t p0, unsigned long long *acc, uint64_t *pr,
+                          uint64_t *contrib) {
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
+         v += uint64_t(gridDim.x) * blockDim.x) {
+        acc[v] = 0;
+        pr[v] = p0;
+        const uint64_t deg = row_ptr[v + 1] - row_ptr[v];
+        contrib[v] = deg ? p0 / deg : 0;
+    }
 }
 
 // ---- V5 prefix scan of per-entry chunk counts (reduce, scan partials, scan) ----
@@ -460,7 +564,8 @@ __device__ uint64_t block_exclusive_scan(uint64_t x, uint64_t *total) {
     return wbase + inc - x;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(ScanArgs s, uint64_t *block_sums) {
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(ScanArgs s0, uint64_t *block_sums) {
+    const ScanArgs s = resolved(s0);
     uint64_t sum = 0;
     const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
     for (int i = 0; i < kScanItems; ++i) sum += entry_chunks(s, uint32_t(base + i));
@@ -486,8 +591,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(uint64_t *block_sums, 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_write(ScanArgs s, const uint64_t *block_sums,
+__global__ __launch_bounds__(kBlock) void k_scan_write(ScanArgs s0, const uint64_t *block_sums,
                                                        uint64_t *scan) {
+    const ScanArgs s = resolved(s0);
     uint64_t c[kScanItems];
     uint64_t sum = 0;
     const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
@@ -528,26 +634,6 @@ __global__ void k_seed_source(uint32_t *state, uint32_t *bitmap, uint32_t *queue
     }
 }
 
-// ---------------------------------------------------------------------------
-// SSSP near-far: when the near frontier runs dry, the far pile is re-cut at
-// a new split = (smallest live far distance) + delta.  Entries below the old
-// split are stale (those vertices were settled and expanded in an earlier
-// band), entries below the new split become the next near frontier, the rest
-// stay in the (compacted) far pile.  Distances are unchanged: only the order
-// in which vertices are expanded differs, so the result stays exact.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_far_min(const uint32_t *far, uint64_t n, const uint32_t *dist,
-                                                     uint32_t split, unsigned long long *ctr) {
-    uint32_t m = 0xFFFFFFFFu;
-    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += uint64_t(gridDim.x) * blockDim.x) {
-        const uint32_t d = dist[far[i]];
-        if (d >= split && d < m) m = d;
-    }
-    for (int o = 32; o > 0; o >>= 1) m = min(m, uint32_t(__shfl_xor(m, o)));
-    if (lane_id() == 0 && m != 0xFFFFFFFFu) atomicMin(&ctr[C_FARMIN], (unsigned long long)m);
-}
-
 __device__ __forceinline__ void push_ballot(bool p, uint32_t v, uint32_t *dst, unsigned long long *count,
                                             int lane) {
     const uint64_t m = __ballot(p);
@@ -558,71 +644,73 @@ __device__ __forceinline__ void push_ballot(bool p, uint32_t v, uint32_t *dst, u
     if (p) dst[base + rank_below(m)] = v;
 }
 
-// Cuts a pile at `cut`: entries below `stale` are dropped (already settled),
-// entries in [stale, cut) move to `dst` (marking `dst_bits` when given),
-// the rest are compacted into `keep`.  Moved and dropped entries leave
-// `src_bits`.
-__global__ __launch_bounds__(kBlock) void k_far_split(const uint32_t *pile, uint64_t n, const uint32_t *dist,
-                                                       uint32_t stale, uint32_t cut, uint32_t *src_bits,
-                                                       uint32_t *dst_bits, uint32_t *dst, int dst_ctr,
-                                                       uint32_t *keep_out, int keep_ctr,
-                                                       unsigned long long *ctr) {
-    const int lane = lane_id();
-    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-    // whole waves step together so the ballots see every lane
-    for (uint64_t i0 = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); i0 < n; i0 += stride) {
-        const uint64_t i = i0 + lane;
-        bool move = false, keep = false;
-        uint32_t v = 0;
-        if (i < n) {
-            v = pile[i];
-            const uint32_t d = dist[v];
-            if (d < cut) {
-                atomicAnd(&src_bits[v >> 5], ~(1u << (v & 31u)));
-                move = d >= stale;
-                if (move && dst_bits) atomicOr(&dst_bits[v >> 5], 1u << (v & 31u));
-            } else {
-                keep = true;
-            }
-        }
-        push_ballot(move, v, dst, &ctr[dst_ctr], lane);
-        push_ballot(keep, v, keep_out, &ctr[keep_ctr], lane);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Ordered frontier: the next frontier is collected as a bitmap during the
 // scan and listed here in ascending id order (so the next level reads
-// neighbour lists in edge-array order), clearing the bitmap as it goes.
+// neighbour lists in edge-array order), clearing the listed marks.
+// SSSP bands (dist != null): a marked vertex is listed only when its distance
+// is below `split`; the others stay marked for a later band, and the smallest
+// of their distances d is kept, as 2^32 - d by atomicMax, in ctr[C_BANDMIN].
 // ---------------------------------------------------------------------------
 constexpr int kBitsPerThread = 16;                     // words per thread
 constexpr int kBitsTile = kBlock * kBitsPerThread;     // words per block
 
-__global__ __launch_bounds__(kBlock) void k_bits_count(const uint32_t *bits, uint64_t words,
-                                                        uint64_t *block_sums) {
+__device__ __forceinline__ uint32_t band_select(uint32_t w, uint64_t word, const uint32_t *dist, uint32_t split,
+                                                uint32_t &rest_min) {
+    if (!dist) return w;
+    uint32_t m = 0;
+    for (uint32_t x = w; x; x &= x - 1) {
+        const int b = __ffs(x) - 1;
+        const uint32_t d = dist[word * 32 + b];
+        if (d < split) m |= 1u << b;
+        else rest_min = min(rest_min, d);
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bits_count(const uint32_t *bits, uint64_t words, const uint32_t *dist,
+                                                        uint32_t split, uint64_t *block_sums,
+                                                        unsigned long long *ctr) {
     uint64_t c = 0;
+    uint32_t rest = 0xFFFFFFFFu;
     const uint64_t base = uint64_t(blockIdx.x) * kBitsTile + uint64_t(threadIdx.x) * kBitsPerThread;
     for (int i = 0; i < kBitsPerThread; ++i)
-        if (base + i < words) c += __popc(bits[base + i]);
+        if (base + i < words) {
+            const uint32_t w = bits[base + i];
+            if (w) c += __popc(band_select(w, base + i, dist, split, rest));
+        }
     uint64_t tot;
     (void)block_exclusive_scan(c, &tot);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+    if (dist) {
+        for (int o = 32; o > 0; o >>= 1) rest = min(rest, uint32_t(__shfl_xor(rest, o)));
+        if (lane_id() == 0 && rest != 0xFFFFFFFFu) atomicMax(&ctr[C_BANDMIN], 0x100000000ull - rest);
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t words,
-                                                        const uint64_t *block_offsets, uint32_t nb,
+__global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t words, const uint32_t *dist,
+                                                        uint32_t split, const uint64_t *block_offsets, uint32_t nb,
                                                         uint32_t *queue, unsigned long long *ctr) {
     const uint64_t base = uint64_t(blockIdx.x) * kBitsTile + uint64_t(threadIdx.x) * kBitsPerThread;
+    uint32_t sel[kBitsPerThread];
+    uint32_t rest = 0xFFFFFFFFu;  // not used here: k_bits_count reported it
     uint64_t c = 0;
-    for (int i = 0; i < kBitsPerThread; ++i)
-        if (base + i < words) c += __popc(bits[base + i]);
+#pragma unroll
+    for (int i = 0; i < kBitsPerThread; ++i) {
+        sel[i] = 0;
+        if (base + i < words) {
+            const uint32_t w = bits[base + i];
+            if (w) sel[i] = band_select(w, base + i, dist, split, rest);
+        }
+        c += __popc(sel[i]);
+    }
     uint64_t tot;
     uint64_t pos = block_offsets[blockIdx.x] + block_exclusive_scan(c, &tot);
+#pragma unroll
     for (int i = 0; i < kBitsPerThread; ++i) {
-        if (base + i >= words) break;
-        uint32_t w = bits[base + i];
+        uint32_t w = sel[i];
         if (!w) continue;
-        bits[base + i] = 0u;
+        bits[base + i] &= ~w;  // this thread alone owns the word during the listing
         while (w) {
             const int b = __ffs(w) - 1;
             w &= w - 1;
@@ -740,26 +828,12 @@ static emogi_status_t ensure_pool(emogi_graph_s *g, int algo) {
             return st;
     if ((st = dalloc(reinterpret_cast<void **>(&p.bitmap), ((V + 31) / 32) * sizeof(uint32_t))) != EMOGI_OK)
         return st;
-    if (algo != A_BFS &&
+    if (algo == A_CC &&
         (st = dalloc(reinterpret_cast<void **>(&p.stamp), V * sizeof(uint32_t))) != EMOGI_OK)
         return st;
     if (algo == A_CC &&
         (st = dalloc(reinterpret_cast<void **>(&p.cc_probe), kCcProbe * sizeof(uint32_t))) != EMOGI_OK)
         return st;
-    if (algo == A_SSSP && g->sssp_delta > 0) {
-        for (int i = 0; i < 2; ++i)
-            if ((st = dalloc(reinterpret_cast<void **>(&p.far[i]), V * sizeof(uint32_t))) != EMOGI_OK)
-                return st;
-        for (int i = 0; i < 2; ++i)
-            if ((st = dalloc(reinterpret_cast<void **>(&p.mid[i]), V * sizeof(uint32_t))) != EMOGI_OK)
-                return st;
-        if ((st = dalloc(reinterpret_cast<void **>(&p.farbits), ((V + 31) / 32) * sizeof(uint32_t))) !=
-            EMOGI_OK)
-            return st;
-        if ((st = dalloc(reinterpret_cast<void **>(&p.midbits), ((V + 31) / 32) * sizeof(uint32_t))) !=
-            EMOGI_OK)
-            return st;
-    }
     if ((st = dalloc(reinterpret_cast<void **>(&p.counters), C_COUNT * sizeof(unsigned long long))) != EMOGI_OK)
         return st;
     if (!p.host_counters) {
@@ -793,6 +867,8 @@ static emogi_status_t ensure_scan(emogi_graph_s *g, uint64_t n) {
     return EMOGI_OK;
 }
 
+bool sched_needs_features(const emogi_graph_s *g);
+
 template <class ColT, int A>
 static void launch_variant(int var, const ScanArgs &s, const OpArgs &a, hipStream_t stream) {
     const uint64_t n = s.n;
@@ -822,6 +898,34 @@ static void launch_variant(int var, const ScanArgs &s, const OpArgs &a, hipStrea
     }
 }
 
+// Levels per host wait for BFS: the setting, or (0) 8 on graphs of up to
+// 2^22 vertices and 1 above; always 1 when the scheduler needs per-level
+// features or timings.
+static uint32_t level_batch(const emogi_graph_s *g) {
+    if (sched_needs_features(g) || g->sched_mode == EMOGI_SCHED_PROBE) return 1;
+    if (g->level_batch) return g->level_batch;
+    return g->V <= (uint64_t(1) << 22) ? 8u : 1u;
+}
+
+static emogi_status_t ensure_level_blocks(emogi_graph_s *g, uint32_t lb) {
+    Pool &p = g->pool;
+    if (p.level_ctr && p.level_cap >= lb) return EMOGI_OK;
+    if (p.level_ctr) (void)hipFree(p.level_ctr);
+    if (p.level_host) (void)hipHostFree(p.level_host);
+    p.level_ctr = nullptr;
+    p.level_host = nullptr;
+    p.level_cap = 0;
+    const size_t bytes = size_t(lb) * C_COUNT * sizeof(unsigned long long);
+    if (hipMalloc(reinterpret_cast<void **>(&p.level_ctr), bytes) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&p.level_host), bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("level-batch counter allocation failed");
+        return EMOGI_E_OOM_DEVICE;
+    }
+    p.level_cap = lb;
+    return EMOGI_OK;
+}
+
 // The built-in rule of thumb (also the learned scheduler's fallback).
 int heuristic_variant(const emogi_graph_s *g, uint64_t n) {
     if (n >= 2048) return EMOGI_V5_BALANCED;
@@ -831,7 +935,6 @@ int heuristic_variant(const emogi_graph_s *g, uint64_t n) {
 
 int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue, hipStream_t stream,
                    float *features);
-bool sched_needs_features(const emogi_graph_s *g);
 emogi_status_t sched_begin(emogi_graph_s *g, hipStream_t stream);
 emogi_status_t sched_prefetch(emogi_graph_s *g, int algo, const uint32_t *queue, unsigned long long *counters,
                               hipStream_t stream);
@@ -857,22 +960,16 @@ static emogi_status_t snapshot(emogi_graph_s *g, int algo, uint32_t *out, hipStr
     };
     EMOGI_HIP_TRY(cp(out, p.snap_state, V * 4), EMOGI_E_HIP);
     if (algo != A_CC) EMOGI_HIP_TRY(cp(p.bitmap, p.snap_bitmap, words * 4), EMOGI_E_HIP);
-    if (algo != A_BFS) EMOGI_HIP_TRY(cp(p.stamp, p.snap_stamp, V * 4), EMOGI_E_HIP);
-    if (algo == A_SSSP && p.farbits) {
-        if (!p.snap_farbits && hipMalloc(&p.snap_farbits, words * 4) != hipSuccess) {
+    if (algo == A_CC && p.stamp) EMOGI_HIP_TRY(cp(p.stamp, p.snap_stamp, V * 4), EMOGI_E_HIP);
+    if (algo == A_SSSP) {
+        // marks of improved vertices waiting for a later band survive the listing
+        if (!p.snap_nextbits && hipMalloc(&p.snap_nextbits, words * 4) != hipSuccess) {
             (void)hipGetLastError();
-            p.snap_farbits = nullptr;
+            p.snap_nextbits = nullptr;
             set_error("probe snapshot allocation failed");
             return EMOGI_E_OOM_DEVICE;
         }
-        EMOGI_HIP_TRY(cp(p.farbits, p.snap_farbits, words * 4), EMOGI_E_HIP);
-        if (!p.snap_midbits && hipMalloc(&p.snap_midbits, words * 4) != hipSuccess) {
-            (void)hipGetLastError();
-            p.snap_midbits = nullptr;
-            set_error("probe snapshot allocation failed");
-            return EMOGI_E_OOM_DEVICE;
-        }
-        EMOGI_HIP_TRY(cp(p.midbits, p.snap_midbits, words * 4), EMOGI_E_HIP);
+        EMOGI_HIP_TRY(cp(p.nextbits, p.snap_nextbits, words * 4), EMOGI_E_HIP);
     }
     return EMOGI_OK;
 }
@@ -971,8 +1068,6 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             hipLaunchKernelGGL(k_fill, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V, 0xFFFFFFFFu);
             EMOGI_HIP_TRY(hipMemsetAsync(p.bitmap, 0, ((V + 31) / 32) * sizeof(uint32_t), stream),
                           EMOGI_E_HIP);
-            if (algo == A_SSSP)
-                EMOGI_HIP_TRY(hipMemsetAsync(p.stamp, 0, V * sizeof(uint32_t), stream), EMOGI_E_HIP);
             hipLaunchKernelGGL(k_seed_source, dim3(1), dim3(64), 0, stream, out, p.bitmap, p.queue[0],
                                uint32_t(src), algo == A_BFS ? 1 : 0);
             n = 1;
@@ -992,8 +1087,10 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     int cur = 0;
     uint32_t iter = 0;
     bool overflow_seen = false;
-    // SSSP near-far bands (0 = plain label correcting: every improvement re-enters at once)
-    const bool ordered = g->ordered_frontier && kalgo != A_LINK && V > 0;
+    // The next frontier is listed from a bitmap (ordered) for BFS and CC label
+    // propagation when asked, and always for SSSP, whose marks also hold the
+    // improved vertices that wait for a later distance band.
+    const bool ordered = (g->ordered_frontier || algo == A_SSSP) && kalgo != A_LINK && V > 0;
     if (ordered) {
         if ((st = ensure_scan(g, V)) != EMOGI_OK) return st;
         if (!p.nextbits && hipMalloc(&p.nextbits, ((V + 31) / 32) * sizeof(uint32_t)) != hipSuccess) {
@@ -1004,83 +1101,140 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         }
         EMOGI_HIP_TRY(hipMemsetAsync(p.nextbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
     }
-    const bool nearfar = algo == A_SSSP && g->sssp_delta > 0 && V > 0;
+    // SSSP distance bands (Sec. 5.1 leaves the SSSP algorithm open; this is a
+    // near-far worklist): a round expands the marked vertices whose distance is
+    // below `split`; when none is left the split moves to the smallest marked
+    // distance + delta.  delta = 0: one band, plain label correcting.
     const uint32_t delta = g->sssp_delta;
-    uint32_t split = nearfar ? delta : 0xFFFFFFFFu;
-    uint64_t far_n = 0;
-    int fcur = 0;
-    if (nearfar) {
-        EMOGI_HIP_TRY(hipMemsetAsync(p.farbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
-        EMOGI_HIP_TRY(hipMemsetAsync(p.midbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
-    }
-    // mid pile: the next kMidBands bands, so the large far pile is re-read
-    // only when the mid pile runs dry
-    const uint64_t kMidBands = 16;
-    uint32_t mid_limit = nearfar ? uint32_t(std::min<uint64_t>(uint64_t(split) + kMidBands * delta, 0xFFFFFFFFull))
-                                 : 0xFFFFFFFFu;
-    uint64_t mid_n = 0;
-    int mcur = 0;
-    // smallest live (>= split) distance in a pile, or ~0 when none
-    auto pile_min = [&](const uint32_t *pile, uint64_t len, unsigned long long *m) -> emogi_status_t {
-        EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
-        EMOGI_HIP_TRY(hipMemsetAsync(&p.counters[C_FARMIN], 0xFF, sizeof(unsigned long long), stream),
-                      EMOGI_E_HIP);
-        hipLaunchKernelGGL(k_far_min, dim3(fill_grid(len)), dim3(kBlock), 0, stream, pile, len, out, split,
-                           p.counters);
-        EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
-                                     hipMemcpyDeviceToHost, stream),
-                      EMOGI_E_HIP);
-        EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
-        *m = p.host_counters[C_FARMIN];
-        return EMOGI_OK;
+    uint32_t split = (algo == A_SSSP && delta > 0) ? delta : 0xFFFFFFFFu;
+    const uint32_t *band_dist = algo == A_SSSP ? out : nullptr;
+    const uint64_t words = (V + 31) / 32;
+    const unsigned nbw = unsigned((words + kBitsTile - 1) / kBitsTile);
+    // Lists the marks (below `cut` for SSSP) into `queue` in id order; the
+    // count lands in counters[C_NEXT], the smallest mark left in C_BANDMIN.
+    auto list_marks = [&](uint32_t *queue, uint32_t cut) {
+        hipLaunchKernelGGL(k_bits_count, dim3(nbw), dim3(kBlock), 0, stream, p.nextbits, words, band_dist, cut,
+                           p.block_sums, p.counters);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nbw);
+        hipLaunchKernelGGL(k_bits_write, dim3(nbw), dim3(kBlock), 0, stream, p.nextbits, words, band_dist, cut,
+                           p.block_sums, nbw, queue, p.counters);
     };
-    auto pile_cut = [&](const uint32_t *pile, uint64_t len, uint32_t cut, uint32_t *src_bits, uint32_t *dst_bits,
-                        uint32_t *dst, int dst_ctr, uint32_t *keep, int keep_ctr) -> emogi_status_t {
-        EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
-        hipLaunchKernelGGL(k_far_split, dim3(fill_grid(len)), dim3(kBlock), 0, stream, pile, len, out, split, cut,
-                           src_bits, dst_bits, dst, dst_ctr, keep, keep_ctr, p.counters);
-        EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
-        EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
-                                     hipMemcpyDeviceToHost, stream),
-                      EMOGI_E_HIP);
-        EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
-        return EMOGI_OK;
-    };
+    p.host_counters[C_BANDMIN] = 0;
     // The scheduler's features and pick for the next frontier are computed
-    // behind each level and come back with its counters (have_pick); a
-    // frontier cut from an SSSP pile, or the first one, is scored on its own.
+    // behind each level and come back with its counters (have_pick); the
+    // first frontier, and one opened by an SSSP band step, is scored on its own.
     const bool prefetch = V > 0 && sched_needs_features(g);
     bool have_pick = false;
     if (prefetch && (st = sched_begin(g, stream)) != EMOGI_OK) return st;
-    while (n > 0 || mid_n > 0 || far_n > 0) {
-        if (n == 0) {
-            have_pick = false;
-            // near frontier exhausted: refill the mid pile from the far pile if
-            // needed, then cut the mid pile at (live minimum + delta)
-            unsigned long long m;
-            if (mid_n == 0) {
-                if ((st = pile_min(p.far[fcur], far_n, &m)) != EMOGI_OK) return st;
-                const uint32_t new_mid = m == ~0ull ? split
-                    : uint32_t(std::min<uint64_t>(m + kMidBands * delta, 0xFFFFFFFFull));
-                if ((st = pile_cut(p.far[fcur], far_n, new_mid, p.farbits, p.midbits, p.mid[mcur], C_MID,
-                                   p.far[fcur ^ 1], C_FAR)) != EMOGI_OK)
-                    return st;
-                far_n = p.host_counters[C_FAR];
-                mid_n = p.host_counters[C_MID];
-                fcur ^= 1;
-                mid_limit = std::max(mid_limit, new_mid);
-                if (mid_n == 0) continue;
+
+    // BFS level batches: on small graphs the host's wait after each level
+    // costs more than the level, so `lb` levels are enqueued at once.  Each
+    // level has its own counter block; its kernels read the frontier length
+    // the previous level left there and do nothing once it is zero, so
+    // enqueuing past the last level is harmless.  The host waits once per
+    // batch.  The variant is fixed for the batch (the host cannot see the
+    // frontiers), pushes go through the LDS-staged queue.
+    const uint32_t lb = (algo == A_BFS && V > 0) ? level_batch(g) : 1;
+    if (lb > 1) {
+        if ((st = ensure_level_blocks(g, lb)) != EMOGI_OK) return st;
+        const int m = g->sched_mode;
+        const int var = (m >= 0 && m < EMOGI_NUM_VARIANTS) ? m : heuristic_variant(g, V);
+        const unsigned nb_max = unsigned((V + kScanTile) / kScanTile);
+        if (var == EMOGI_V5_BALANCED && (st = ensure_scan(g, V)) != EMOGI_OK) return st;
+        while (n > 0) {
+            if (iter >= cap) {
+                (void)hipStreamSynchronize(stream);
+                set_error("iteration cap %llu reached", (unsigned long long)cap);
+                return EMOGI_E_NOCONVERGE;
             }
-            if ((st = pile_min(p.mid[mcur], mid_n, &m)) != EMOGI_OK) return st;
-            const uint64_t ns64 = m == ~0ull ? uint64_t(split) : std::min<uint64_t>(m + delta, mid_limit);
-            const uint32_t new_split = uint32_t(std::max<uint64_t>(ns64, split));
-            if ((st = pile_cut(p.mid[mcur], mid_n, new_split, p.midbits, nullptr, p.queue[cur], C_NEXT,
-                               p.mid[mcur ^ 1], C_MID)) != EMOGI_OK)
-                return st;
+            EMOGI_HIP_TRY(hipMemsetAsync(p.level_ctr, 0, size_t(lb) * C_COUNT * sizeof(unsigned long long), stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
+            for (uint32_t i = 0; i < lb; ++i) {
+                ScanArgs s;
+                s.queue = p.queue[cur];
+                s.n = i == 0 ? uint32_t(n) : uint32_t(V);  // later levels: V only sizes the grids
+                s.n_dev = i == 0 ? nullptr : &p.level_ctr[(i - 1) * C_COUNT + C_NEXT];
+                s.row_ptr = g->row_ptr;
+                s.col = g->col;
+                s.w = g->weights;
+                s.next = p.queue[cur ^ 1];
+                s.align_mask = uint64_t(align_elems) - 1;
+                s.req_unit = g->request_unit;
+                s.col_bytes = g->col_bytes;
+                s.chunk_scan = nullptr;
+                s.tier = tier_view(g);
+                OpArgs a;
+                a.state = out;
+                a.bitmap = p.bitmap;
+                a.stamp = nullptr;
+                a.tag = iter + i + 1;
+                a.V = uint32_t(V);
+                a.ctr = &p.level_ctr[i * C_COUNT];
+                a.nextbits = nullptr;
+                if (var == EMOGI_V5_BALANCED) {
+                    const unsigned nb = i == 0 ? unsigned((n + kScanTile) / kScanTile) : nb_max;
+                    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums);
+                    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nb);
+                    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums,
+                                       p.chunk_scan);
+                    s.chunk_scan = p.chunk_scan;
+                }
+                if (g->col_bytes == 8)
+                    launch_variant<uint64_t, A_BFS>(var, s, a, stream);
+                else
+                    launch_variant<uint32_t, A_BFS>(var, s, a, stream);
+                cur ^= 1;
+            }
+            EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipMemcpyAsync(p.level_host, p.level_ctr, size_t(lb) * C_COUNT * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+            float ms = 0.f;
+            EMOGI_HIP_TRY(hipEventElapsedTime(&ms, g->ev_k0, g->ev_k1), EMOGI_E_HIP);
+            S.expand_ms += ms;
+            uint32_t ran = 0;
+            for (uint32_t i = 0; i < lb && n > 0; ++i, ++ran) {
+                const unsigned long long *hc = &p.level_host[i * C_COUNT];
+                if (iter < EMOGI_MAX_LEVEL_STATS) {
+                    S.level_variant[iter] = uint8_t(var);
+                    S.level_frontier[iter] = uint32_t(n);
+                    S.level_edges[iter] = hc[C_EDGES];
+                    S.level_count = iter + 1;
+                }
+                S.variant_hist[var] += 1;
+                S.expand_launches += 1;
+                S.edges_scanned += hc[C_EDGES];
+                S.tier_edges += hc[C_TIER];
+                S.request_bytes += hc[C_REQBYTES];
+                S.vertices_expanded += hc[C_VERTS];
+                n = hc[C_NEXT];
+                ++iter;
+            }
+            // the batch's time, shared evenly by the levels that had work
+            for (uint32_t i = 0; i < ran; ++i)
+                if (iter - ran + i < EMOGI_MAX_LEVEL_STATS) S.level_ms[iter - ran + i] = ms / float(ran);
+        }
+    }
+    while (true) {
+        if (n == 0) {
+            // SSSP: the band is exhausted; open the next one at the smallest
+            // marked distance, or stop when nothing is marked
+            have_pick = false;
+            const unsigned long long bm = p.host_counters[C_BANDMIN];
+            if (algo != A_SSSP || bm == 0) break;
+            const uint64_t m = 0x100000000ull - bm;
+            split = uint32_t(std::min<uint64_t>(std::max<uint64_t>(m + delta, split), 0xFFFFFFFFull));
+            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
+            list_marks(p.queue[cur], split);
+            EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
             n = p.host_counters[C_NEXT];
-            mid_n = p.host_counters[C_MID];
-            mcur ^= 1;
-            split = new_split;
             continue;
         }
         if (iter >= cap) {
@@ -1095,6 +1249,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             ScanArgs s;
             s.queue = queue;
             s.n = uint32_t(n);
+            s.n_dev = nullptr;
             s.row_ptr = g->row_ptr;
             s.col = g->col;
             s.w = g->weights;
@@ -1111,12 +1266,6 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             a.tag = iter + 1;  // BFS: level of the next frontier; SSSP/CC: round
             a.V = uint32_t(V);
             a.ctr = p.counters;
-            a.split = split;
-            a.far = nearfar ? p.far[fcur] + far_n : nullptr;
-            a.mid = nearfar ? p.mid[mcur] + mid_n : nullptr;
-            a.midbits = p.midbits;
-            a.mid_limit = mid_limit;
-            a.farbits = p.farbits;
             a.nextbits = ordered ? p.nextbits : nullptr;
             EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
                           EMOGI_E_HIP);
@@ -1145,13 +1294,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
             if (ordered) {
-                const uint64_t words = (V + 31) / 32;
-                const unsigned nbw = unsigned((words + kBitsTile - 1) / kBitsTile);
-                hipLaunchKernelGGL(k_bits_count, dim3(nbw), dim3(kBlock), 0, stream, p.nextbits, words,
-                                   p.block_sums);
-                hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nbw);
-                hipLaunchKernelGGL(k_bits_write, dim3(nbw), dim3(kBlock), 0, stream, p.nextbits, words,
-                                   p.block_sums, nbw, s.next, p.counters);
+                list_marks(s.next, split);
                 EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             }
             if (prefetch) {
@@ -1210,8 +1353,6 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         S.vertices_expanded += hc[C_VERTS];
         if (hc[C_OVERFLOW]) overflow_seen = true;
         n = hc[C_NEXT];
-        far_n += hc[C_FAR];
-        mid_n += hc[C_MID];
         if (identity) {
             identity = false;
             cur = 0;
@@ -1245,6 +1386,111 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     return EMOGI_OK;
 }
 
+static emogi_status_t pagerank(emogi_graph_s *g, uint32_t iters, uint32_t F, uint64_t d, uint64_t *out,
+                               hipStream_t stream) {
+    if (!g || !out) {
+        set_error("null graph or output");
+        return EMOGI_E_INVALID;
+    }
+    if (!(g->flags & EMOGI_F_SYMMETRIC)) {
+        set_error("PageRank (pull form) needs a graph created with EMOGI_F_SYMMETRIC");
+        return EMOGI_E_NOT_SYMMETRIC;
+    }
+    if (F < 1 || F > 62 || d >= (uint64_t(1) << F)) {
+        set_error("PageRank needs 1 <= frac_bits <= 62 and damping_fixed < 2^frac_bits");
+        return EMOGI_E_INVALID;
+    }
+    {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, out) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();
+            set_error("output must be device memory");
+            return EMOGI_E_INVALID;
+        }
+    }
+    emogi_status_t st = ensure_pool(g, A_BFS);
+    if (st != EMOGI_OK) return st;
+    Pool &p = g->pool;
+    const uint64_t V = g->V;
+    emogi_stats_t &S = g->stats;
+    memset(&S, 0, sizeof(S));
+    S.request_unit = g->request_unit;
+    EMOGI_HIP_TRY(hipEventRecord(g->ev_begin, stream), EMOGI_E_HIP);
+    if (V > 0) {
+        for (void **b : {reinterpret_cast<void **>(&p.pr_acc), reinterpret_cast<void **>(&p.pr_contrib)})
+            if (!*b && hipMalloc(b, V * sizeof(uint64_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                *b = nullptr;
+                set_error("hipMalloc of the PageRank buffers failed");
+                return EMOGI_E_OOM_DEVICE;
+            }
+        if ((st = ensure_scan(g, V)) != EMOGI_OK) return st;
+        const uint64_t one = uint64_t(1) << F;
+        ScanArgs s{};
+        s.queue = nullptr;  // every vertex, in id order
+        s.n = uint32_t(V);
+        s.n_dev = nullptr;
+        s.row_ptr = g->row_ptr;
+        s.col = g->col;
+        s.w = nullptr;
+        s.next = nullptr;
+        s.align_mask = uint64_t(std::max<uint32_t>(1, g->request_unit / g->col_bytes)) - 1;
+        s.req_unit = g->request_unit;
+        s.col_bytes = g->col_bytes;
+        s.tier = tier_view(g);
+        const unsigned nb = unsigned((V + kScanTile) / kScanTile);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nb);
+        hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums, p.chunk_scan);
+        s.chunk_scan = p.chunk_scan;
+        hipLaunchKernelGGL(k_pr_init, dim3(fill_grid(V)), dim3(kBlock), 0, stream, g->row_ptr, V, one / V,
+                           p.pr_acc, out, p.pr_contrib);
+        EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+        PrArgs pa{p.pr_contrib, p.pr_acc, p.counters};
+        for (uint32_t t = 0; t < iters; ++t) {
+            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
+            if (g->col_bytes == 8)
+                hipLaunchKernelGGL(k_pr_pull<uint64_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, s, pa);
+            else
+                hipLaunchKernelGGL(k_pr_pull<uint32_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, s, pa);
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
+            hipLaunchKernelGGL(k_pr_finish, dim3(fill_grid(V)), dim3(kBlock), 0, stream, g->row_ptr, V, (one - d) / V,
+                               d, F, p.pr_acc, out, p.pr_contrib);
+            EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, stream),
+                          EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+            float ms = 0.f;
+            EMOGI_HIP_TRY(hipEventElapsedTime(&ms, g->ev_k0, g->ev_k1), EMOGI_E_HIP);
+            const unsigned long long *hc = p.host_counters;
+            if (t < EMOGI_MAX_LEVEL_STATS) {
+                S.level_variant[t] = uint8_t(EMOGI_V5_BALANCED);
+                S.level_frontier[t] = uint32_t(V);
+                S.level_ms[t] = ms;
+                S.level_edges[t] = hc[C_EDGES];
+                S.level_count = t + 1;
+            }
+            S.variant_hist[EMOGI_V5_BALANCED] += 1;
+            S.expand_ms += ms;
+            S.expand_launches += 1;
+            S.edges_scanned += hc[C_EDGES];
+            S.tier_edges += hc[C_TIER];
+            S.request_bytes += hc[C_REQBYTES];
+            S.vertices_expanded += hc[C_VERTS];
+        }
+    }
+    S.iterations = iters;
+    S.useful_link_bytes = (S.edges_scanned - S.tier_edges) * g->col_bytes;
+    EMOGI_HIP_TRY(hipEventRecord(g->ev_end, stream), EMOGI_E_HIP);
+    EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+    float total = 0.f;
+    EMOGI_HIP_TRY(hipEventElapsedTime(&total, g->ev_begin, g->ev_end), EMOGI_E_HIP);
+    S.total_ms = total;
+    return EMOGI_OK;
+}
+
 }  // namespace emogi
 
 using namespace emogi;
@@ -1261,6 +1507,11 @@ emogi_status_t emogi_sssp(emogi_graph_t g, uint64_t src, uint32_t *dist, void *s
 
 emogi_status_t emogi_cc(emogi_graph_t g, uint32_t *labels, void *stream) {
     return traverse(g, A_CC, 0, labels, static_cast<hipStream_t>(stream));
+}
+
+emogi_status_t emogi_pagerank(emogi_graph_t g, uint32_t iters, uint32_t frac_bits, uint64_t damping_fixed,
+                              uint64_t *scores, void *stream) {
+    return pagerank(g, iters, frac_bits, damping_fixed, scores, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

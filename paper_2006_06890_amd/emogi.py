@@ -190,11 +190,13 @@ def lib():
             "emogi_set_sssp_delta": (i32, [p, u32]),
             "emogi_set_cc_algorithm": (i32, [p, i32]),
             "emogi_set_hbm_tier": (i32, [p, u64, p, p]),
+            "emogi_set_level_batch": (i32, [p, u32]),
             "emogi_set_frontier_order": (i32, [p, i32]),
             "emogi_set_scheduler_weights": (i32, [p, p, sz]),
             "emogi_bfs": (i32, [p, u64, p, p]),
             "emogi_sssp": (i32, [p, u64, p, p]),
             "emogi_cc": (i32, [p, p, p]),
+            "emogi_pagerank": (i32, [p, u32, u32, u64, p, p]),
             "emogi_last_stats": (i32, [p, ctypes.POINTER(Stats)]),
             "emogi_num_vertices": (u64, [p]),
             "emogi_num_edges": (u64, [p]),
@@ -336,6 +338,10 @@ class Graph:
         check(lib().emogi_set_cc_algorithm(
             self._h, {"label_propagation": 0, "sampled_union_find": 1}[name]))
 
+    def set_level_batch(self, levels):
+        """BFS levels enqueued per host wait (0: automatic, 1: per-level waits)."""
+        check(lib().emogi_set_level_batch(self._h, int(levels)))
+
     def set_hbm_tier(self, budget_bytes):
         """Copies the highest-degree vertices' lists that fit in budget_bytes
         into GPU memory (0 removes the tier); returns (vertices, bytes) held."""
@@ -392,6 +398,23 @@ class Graph:
         if not 1 <= s.shape[0] <= 64:
             raise ValueError("1..64 sources")
         return s
+
+    def pagerank(self, iters, frac_bits=40, damping_fixed=None, out=None, stream=None):
+        """Fixed-point PageRank (emogi_pagerank); returns an int64 CUDA tensor
+        holding the uint64 scores (view it as uint64 on the host).
+        damping_fixed defaults to floor(0.85 * 2^frac_bits)."""
+        import torch
+        if damping_fixed is None:
+            damping_fixed = (85 << frac_bits) // 100
+        if out is None:
+            out = torch.empty(max(1, self.num_vertices), dtype=torch.int64, device="cuda")
+        if out.dtype != torch.int64 or not out.is_cuda or not out.is_contiguous():
+            raise TypeError("output must be a contiguous int64 CUDA/HIP tensor")
+        if out.numel() < self.num_vertices:
+            raise ValueError("output tensor too small")
+        check(lib().emogi_pagerank(self._h, int(iters), int(frac_bits), int(damping_fixed), out.data_ptr(),
+                                   _stream_handle(stream)))
+        return out
 
     def bfs_batch(self, srcs, out=None, stream=None):
         """Levels from each source, source-major [n * V] int32 tensor."""
@@ -456,3 +479,8 @@ class Graph:
 def to_u32(t):
     """int32 device tensor -> uint32 numpy array on the host."""
     return t.detach().cpu().numpy().view(np.uint32)
+
+
+def to_u64(t):
+    """int64 device tensor -> uint64 numpy array on the host."""
+    return t.detach().cpu().numpy().view(np.uint64)

@@ -224,6 +224,60 @@ def test_directed_sssp_delta(gpu_device):
                 np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(g.row_ptr, g.col, g.weights, s))
 
 
+@pytest.mark.parametrize("batch", [1, 2, 8, 64])
+@pytest.mark.parametrize("name", ["rmat13", "uniform11", "path300", "star5000", "tree1000", "cliques",
+                                  "single", "edgeless7"])
+def test_bfs_level_batches(gpu_device, name, batch):
+    """BFS with several levels enqueued per host wait (frontier lengths read
+    on the device): same levels and per-level statistics as one level per
+    wait, for every variant and both edge widths."""
+    import torch
+    E = _emogi()
+    g = graphs()[name]
+    out = torch.empty(max(1, g.num_vertices), dtype=torch.int32, device="cuda")
+    for col_bytes in (4, 8):
+        rp, col, w = _with_col(g, col_bytes)
+        with E.Graph(rp, col, w, placement="host_zero_copy", symmetric=True) as G:
+            G.set_level_batch(batch)
+            for v in VARIANTS:
+                G.set_variant(v)
+                for s in _sources(g):
+                    exp = oracle.bfs(g.row_ptr, g.col, s)
+                    G.bfs(s, out)
+                    np.testing.assert_array_equal(E.to_u32(out)[: g.num_vertices], exp,
+                                                  err_msg=f"{name} e{col_bytes} V{v} s{s} batch {batch}")
+                    st = G.stats()
+                    reached = exp != E.INF
+                    assert st["iterations"] == int(exp[reached].max()) + 1
+                    assert st["edges_scanned"] == oracle.reached_edges(g.row_ptr, exp)
+                    levels = np.bincount(exp[reached].astype(np.int64))
+                    assert st["level_frontier"] == levels.tolist()
+
+
+@pytest.mark.parametrize("name", ["rmat13", "uniform11", "path300", "star5000"])
+def test_sssp_unit_band_expands_each_vertex_once(gpu_device, name):
+    """With bands one distance wide (delta = 1) and weights >= 1, a band holds
+    exactly the vertices at the smallest open distance, which are final (the
+    order Dijkstra settles them in): every reached vertex is expanded once and
+    there is one round per distinct finite distance."""
+    import torch
+    E = _emogi()
+    g = graphs()[name]
+    out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+    deg = g.degrees().astype(np.int64)
+    with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True) as G:
+        G.set_sssp_delta(1)
+        for s in _sources(g):
+            exp = oracle.dijkstra(g.row_ptr, g.col, g.weights, s)
+            G.sssp(s, out)
+            np.testing.assert_array_equal(E.to_u32(out), exp)
+            st = G.stats()
+            fin = exp != E.INF
+            assert st["edges_scanned"] == int(deg[fin].sum()), (s, st["edges_scanned"])
+            assert st["vertices_expanded"] == int((fin & (deg > 0)).sum())
+            assert st["iterations"] == np.unique(exp[fin]).shape[0]
+
+
 def test_schedulers_agree(gpu_device):
     E = _emogi()
     g = graphs()["rmat13"]

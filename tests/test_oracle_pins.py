@@ -464,6 +464,107 @@ def test_cc_pin_catches_directed_reach():
 
 
 # ---------------------------------------------------------------------------
+# PageRank in fixed point (EMOGI's fourth workload)
+# ---------------------------------------------------------------------------
+PR_F = 52
+PR_D = (85 << PR_F) // 100  # floor(0.85 * 2^52)
+
+
+def _pr_graphs():
+    """Undirected graphs without isolated vertices (no dangling mass, so the
+    stationary PageRank is networkx's)."""
+    rng = np.random.Generator(np.random.PCG64(17))
+    n = 60
+    tree = [(i, int(rng.integers(0, i))) for i in range(1, n)]
+    extra = [tuple(int(x) for x in rng.integers(0, n, size=2)) for _ in range(90)]
+    return [graphgen.cycle(12), graphgen.complete(9), graphgen.grid(6), graphgen.star(15),
+            graphgen.binary_tree(31), graphgen.path(20), graphgen.from_edges(n, tree + extra)]
+
+
+def pr_networkx_ok(impl):
+    import networkx as nx
+    for g in _pr_graphs():
+        got = impl(g.row_ptr, g.col, PR_F, PR_D, 300).astype(np.float64) / 2.0 ** PR_F
+        G = nx.Graph()
+        G.add_nodes_from(range(g.num_vertices))
+        for u in range(g.num_vertices):
+            for i in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1])):
+                G.add_edge(u, int(g.col[i]))
+        ref = nx.pagerank(G, alpha=0.85, tol=1e-14, max_iter=100000)
+        if np.max(np.abs(got - np.array([ref[v] for v in range(g.num_vertices)]))) > 1e-9:
+            return False
+    return True
+
+
+def pr_symmetry_ok(impl):
+    """Vertex-transitive graphs: every vertex gets the same score, exactly."""
+    for g in (graphgen.cycle(11), graphgen.complete(7)):
+        for iters in (1, 2, 17):
+            pr = impl(g.row_ptr, g.col, PR_F, PR_D, iters)
+            if not np.all(pr == pr[0]):
+                return False
+    return True
+
+
+def _pr_python(rp, col, F, d, iters, own_degree=False, base_kind="damped"):
+    """Python fixed-point iteration with selectable planted mistakes."""
+    V = len(rp) - 1
+    one = 1 << F
+    base = {"damped": (one - d) // V, "none": 0, "undamped": one // V}[base_kind]
+    pr = [one // V] * V
+    for _ in range(iters):
+        nxt = []
+        for v in range(V):
+            s = 0
+            for i in range(int(rp[v]), int(rp[v + 1])):
+                u = int(col[i])
+                deg = int(rp[(v if own_degree else u) + 1] - rp[v if own_degree else u])
+                s += pr[u] // deg
+            nxt.append(base + (d * s >> F))
+        pr = nxt
+    return np.array(pr, dtype=np.uint64)
+
+
+def pr_own_degree(rp, col, F, d, iters):
+    return _pr_python(rp, col, F, d, iters, own_degree=True)
+
+
+def pr_no_base(rp, col, F, d, iters):
+    return _pr_python(rp, col, F, d, iters, base_kind="none")
+
+
+def pr_undamped_base(rp, col, F, d, iters):
+    return _pr_python(rp, col, F, d, iters, base_kind="undamped")
+
+
+def test_pagerank_vs_networkx():
+    assert pr_networkx_ok(oracle.pagerank)
+
+
+def test_pagerank_symmetric_graphs_exactly_uniform():
+    assert pr_symmetry_ok(oracle.pagerank)
+
+
+def test_pagerank_mass_and_python_definition():
+    """Scores never exceed one in total and lose at most one unit per floor;
+    the C oracle and a Python big-integer loop agree bit for bit."""
+    for g in _pr_graphs() + [graphgen.rmat(9, seed=4).to_csr(4)]:
+        for iters in (0, 1, 5):
+            pr = oracle.pagerank(g.row_ptr, g.col, PR_F, PR_D, iters)
+            tot = int(pr.astype(object).sum())
+            assert tot <= 1 << PR_F
+            if np.all(np.diff(g.row_ptr) > 0):
+                assert tot >= (1 << PR_F) - (iters + 1) * (g.num_vertices + g.num_edges + 1)
+        assert np.array_equal(oracle.pagerank(g.row_ptr, g.col, 40, (85 << 40) // 100, 4),
+                              _pr_python(g.row_ptr, g.col, 40, (85 << 40) // 100, 4))
+
+
+@pytest.mark.parametrize("mutant", [pr_own_degree, pr_no_base, pr_undamped_base])
+def test_pins_catch_pagerank_mutants(mutant):
+    assert not (pr_networkx_ok(mutant) and pr_symmetry_ok(mutant))
+
+
+# ---------------------------------------------------------------------------
 # scheduler network reference
 # ---------------------------------------------------------------------------
 def test_mlp_forward_hand_example():
