@@ -167,16 +167,17 @@ emogi_status_t emogi_set_scheduler(emogi_graph_t g, int mode);
  * round trip between its levels (Sec. 4.2 launches one kernel per level and
  * the host checks for termination after each).  1: one level per wait, the
  * variant chosen per level; k > 1 (<= 64): k levels per wait with one
- * variant (the fixed one, else the heuristic's pick for the whole graph) and
- * pushes through the LDS-staged queue; 0 (default): 8 on graphs of up to
- * 2^22 vertices, 1 above.  Always 1 when the scheduler records features,
+ * variant (the fixed one, else a workgroup per vertex below 2^24 edges and
+ * the heuristic's pick for the whole graph above) and
+ * pushes through the LDS-staged queue; 0 (default): 8 on graphs of fewer
+ * than 2^24 edges, 1 above.  Always 1 when the scheduler records features,
  * runs the network or probes.  Results are identical. */
 emogi_status_t emogi_set_level_batch(emogi_graph_t g, uint32_t levels);
 /* SSSP distance band (near-far worklist): every vertex whose distance
  * improves is marked; a round expands, in ascending id order, the marked
  * vertices whose distance is below the current split, and when none is left
  * the split moves to the smallest marked distance + delta.  0 disables the
- * bands (every improved vertex is expanded in the next round).  Default 4.
+ * bands (every improved vertex is expanded in the next round).  Default 3.
  * Results are identical for any value; only the amount of re-expansion
  * changes. */
 emogi_status_t emogi_set_sssp_delta(emogi_graph_t g, uint32_t delta);

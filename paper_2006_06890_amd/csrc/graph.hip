@@ -135,7 +135,7 @@ static void release(emogi_graph_s *g) {
     if (p.features) (void)hipFree(p.features);
     if (p.degree_hist) (void)hipFree(p.degree_hist);
     for (void *x : {(void *)p.snap_state, (void *)p.snap_stamp, (void *)p.snap_bitmap, (void *)p.snap_nextbits,
-                    (void *)p.cc_probe, (void *)p.nextbits})
+                    (void *)p.cc_probe, (void *)p.nextbits, (void *)p.farbits, (void *)p.snap_farbits})
         if (x) (void)hipFree(x);
     if (g->mlp_params) (void)hipFree(g->mlp_params);
     tier_release(g);

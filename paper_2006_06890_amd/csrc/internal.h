@@ -64,6 +64,8 @@ struct Pool {
     uint32_t *snap_stamp = nullptr;
     uint32_t *snap_bitmap = nullptr;
     uint32_t *snap_nextbits = nullptr;        // probe mode: saved SSSP marks
+    uint32_t *farbits = nullptr;              // SSSP: improved beyond the band, not yet expanded
+    uint32_t *snap_farbits = nullptr;
     uint32_t *cc_probe = nullptr;             // CC: roots of probed vertices
     uint32_t *nextbits = nullptr;             // ordered frontier bitmap (SSSP: improved, not yet expanded)
     unsigned long long *pr_acc = nullptr;     // PageRank: per-vertex sums of the iteration
@@ -103,7 +105,7 @@ struct emogi_graph_s {
     enum Kind { NONE, DEVICE, PINNED, MANAGED, BORROWED } col_kind = NONE, w_kind = NONE;
 
     uint32_t request_unit = 256;
-    uint32_t sssp_delta = 4;       // near-far band width; 0 = plain label correcting
+    uint32_t sssp_delta = 3;       // near-far band width; 0 = plain label correcting
     bool cc_sampled = true;        // CC by sampled union-find (else min-label propagation)
     bool ordered_frontier = true;  // list each next frontier in ascending id order
     uint32_t level_batch = 0;      // BFS levels per host wait (0: automatic)

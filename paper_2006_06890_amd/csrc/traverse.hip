@@ -24,6 +24,7 @@
 #include "wave.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -69,7 +70,9 @@ struct OpArgs {
     uint32_t tag;       // BFS: level of the next frontier; CC: round number
     uint32_t V;         // neighbour ids at or above V are ignored (malformed input)
     uint32_t *nextbits; // ordered frontier: next frontier as a bitmap (null: LDS-staged queue);
-                        // SSSP: vertices improved and not yet expanded
+                        // SSSP: vertices improved below the split this round
+    uint32_t split;     // SSSP: improvements at or above it wait for a later band ...
+    uint32_t *farbits;  // ... marked here
     unsigned long long *ctr;
 };
 
@@ -101,7 +104,8 @@ __device__ __forceinline__ void uf_link(uint32_t *parent, uint32_t a, uint32_t b
     }
 }
 
-// Returns 1 when v joins the next frontier (SSSP: when its distance improved), else 0.
+// Returns 1 when v joins the next frontier, 2 when an SSSP improvement waits
+// for a later band, else 0.
 template <int A>
 __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v, uint32_t w) {
     if (v >= a.V) return 0;
@@ -114,8 +118,8 @@ __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v,
         a.state[v] = a.tag;
         return 1;
     } else if (A == A_SSSP) {
-        // SSSP: relax the edge; an improved vertex is marked, and the listing
-        // pass after the round decides in which band it is expanded.
+        // SSSP: relax the edge; an improved vertex joins the next round when
+        // its distance is inside the band, otherwise it waits, marked.
         uint64_t nd = uint64_t(uval) + w;
         if (nd > 0xFFFFFFFEull) {
             atomicOr(&a.bitmap[v >> 5], 1u << (v & 31u));
@@ -124,7 +128,8 @@ __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v,
         }
         if (a.state[v] <= uint32_t(nd)) return 0;
         uint32_t old = atomicMin(&a.state[v], uint32_t(nd));
-        return old > uint32_t(nd) ? 1 : 0;
+        if (old <= uint32_t(nd)) return 0;
+        return uint32_t(nd) < a.split ? 1 : 2;
     } else if (A == A_LINK) {
         uf_link(a.state, uval, v);
         return 0;
@@ -142,13 +147,14 @@ __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v,
 template <int A>
 __device__ __forceinline__ void emit(Stage &st, int r, uint32_t v, uint32_t *next, const OpArgs &a,
                                      int lane) {
+    const uint32_t bit = 1u << (v & 31u);
     if (a.nextbits) {
         // ordered frontier: mark; a listing pass later lists the marks in id order
-        const uint32_t bit = 1u << (v & 31u);
         if (r == 1 && !(a.nextbits[v >> 5] & bit)) atomicOr(&a.nextbits[v >> 5], bit);
     } else {
         stage(st, r == 1, v, next, &a.ctr[C_NEXT], lane);
     }
+    if (A == A_SSSP && r == 2 && !(a.farbits[v >> 5] & bit)) atomicOr(&a.farbits[v >> 5], bit);
 }
 
 struct ScanArgs {
@@ -430,9 +436,9 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
     if (c.kb >= c.kend) open_run<ColT, A>(c, s, a, c.run0 + c.stride);
 }
 
-// V5 main loop, software-pipelined: the loads of the next chunk group are in
-// flight while the current group's neighbours are visited, so a wave keeps
-// host-link reads outstanding through its HBM-side work.
+// V5 main loop: load kUnroll chunks, then visit their neighbours.  (Keeping
+// the next group's loads in flight during the visits measured no faster:
+// vector loads return in issue order, so the visits' HBM loads wait for them.)
 template <class ColT, int A>
 __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s0, OpArgs a) {
     const ScanArgs s = resolved(s0);
@@ -444,20 +450,14 @@ __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s0, OpArgs a) {
     c.total = s.chunk_scan[s.n];
     c.stride = uint64_t(gridDim.x) * kWavesPerBlock * kChunksPerWave;
     open_run<ColT, A>(c, s, a, (uint64_t(blockIdx.x) * kWavesPerBlock + wid) * kChunksPerWave);
-    bool live = c.kb < c.kend;
-    ChunkGroup cur;
-    if (live) load_group<ColT, A>(c, cur, s, a, lane, edges, reqb, verts, tedges);
-    while (live) {
-        const bool more = c.kb < c.kend;
-        ChunkGroup nxt;
-        if (more) load_group<ColT, A>(c, nxt, s, a, lane, edges, reqb, verts, tedges);
+    while (c.kb < c.kend) {
+        ChunkGroup g;
+        load_group<ColT, A>(c, g, s, a, lane, edges, reqb, verts, tedges);
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i) {
-            const int r = cur.ok[i] ? visit<A>(a, cur.uv[i], cur.v[i], cur.w[i]) : 0;
-            emit<A>(st, r, cur.v[i], s.next, a, lane);
+            const int r = g.ok[i] ? visit<A>(a, g.uv[i], g.v[i], g.w[i]) : 0;
+            emit<A>(st, r, g.v[i], s.next, a, lane);
         }
-        if (more) cur = nxt;
-        live = more;
     }
     finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges);
 }
@@ -651,6 +651,7 @@ __device__ __forceinline__ void push_ballot(bool p, uint32_t v, uint32_t *dst, u
 // SSSP bands (dist != null): a marked vertex is listed only when its distance
 // is below `split`; the others stay marked for a later band, and the smallest
 // of their distances d is kept, as 2^32 - d by atomicMax, in ctr[C_BANDMIN].
+// also_clear (optional): the listed vertices' bits are cleared there too.
 // ---------------------------------------------------------------------------
 constexpr int kBitsPerThread = 16;                     // words per thread
 constexpr int kBitsTile = kBlock * kBitsPerThread;     // words per block
@@ -690,7 +691,8 @@ __global__ __launch_bounds__(kBlock) void k_bits_count(const uint32_t *bits, uin
 
 __global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t words, const uint32_t *dist,
                                                         uint32_t split, const uint64_t *block_offsets, uint32_t nb,
-                                                        uint32_t *queue, unsigned long long *ctr) {
+                                                        uint32_t *queue, uint32_t *also_clear,
+                                                        unsigned long long *ctr) {
     const uint64_t base = uint64_t(blockIdx.x) * kBitsTile + uint64_t(threadIdx.x) * kBitsPerThread;
     uint32_t sel[kBitsPerThread];
     uint32_t rest = 0xFFFFFFFFu;  // not used here: k_bits_count reported it
@@ -711,6 +713,7 @@ __global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t 
         uint32_t w = sel[i];
         if (!w) continue;
         bits[base + i] &= ~w;  // this thread alone owns the word during the listing
+        if (also_clear) also_clear[base + i] &= ~w;
         while (w) {
             const int b = __ffs(w) - 1;
             w &= w - 1;
@@ -724,7 +727,8 @@ __global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t 
 // CC by sampled union-find (the labels equal min-label propagation's: every
 // tree's root is its component's smallest id).
 //   1. hook every vertex to its first kCcSample neighbours (reads a prefix
-//      of each list: one small request per vertex);
+//      of each list: one small request per vertex), or, on graphs without
+//      hubs, hook the whole lists of an id range of vertices (see traverse);
 //   2. compress; the most frequent root among sampled vertices is taken as
 //      the large component C;
 //   3. scan the whole lists of the vertices outside C only: an edge with one
@@ -898,13 +902,15 @@ static void launch_variant(int var, const ScanArgs &s, const OpArgs &a, hipStrea
     }
 }
 
-// Levels per host wait for BFS: the setting, or (0) 8 on graphs of up to
-// 2^22 vertices and 1 above; always 1 when the scheduler needs per-level
-// features or timings.
+// Levels per host wait for BFS: the setting, or (0) 8 on graphs of fewer
+// than 2^24 edges and 1 above (measured on R-MAT 16/18/20: batches win up to
+// scale 18; at scale 20 the ordered per-level frontier is worth more than the
+// saved waits); always 1 when the scheduler needs per-level features or
+// timings.
 static uint32_t level_batch(const emogi_graph_s *g) {
     if (sched_needs_features(g) || g->sched_mode == EMOGI_SCHED_PROBE) return 1;
     if (g->level_batch) return g->level_batch;
-    return g->V <= (uint64_t(1) << 22) ? 8u : 1u;
+    return g->E < (uint64_t(1) << 24) ? 8u : 1u;
 }
 
 static emogi_status_t ensure_level_blocks(emogi_graph_s *g, uint32_t lb) {
@@ -963,13 +969,14 @@ static emogi_status_t snapshot(emogi_graph_s *g, int algo, uint32_t *out, hipStr
     if (algo == A_CC && p.stamp) EMOGI_HIP_TRY(cp(p.stamp, p.snap_stamp, V * 4), EMOGI_E_HIP);
     if (algo == A_SSSP) {
         // marks of improved vertices waiting for a later band survive the listing
-        if (!p.snap_nextbits && hipMalloc(&p.snap_nextbits, words * 4) != hipSuccess) {
+        if ((!p.snap_nextbits && hipMalloc(&p.snap_nextbits, words * 4) != hipSuccess) ||
+            (!p.snap_farbits && hipMalloc(&p.snap_farbits, words * 4) != hipSuccess)) {
             (void)hipGetLastError();
-            p.snap_nextbits = nullptr;
             set_error("probe snapshot allocation failed");
             return EMOGI_E_OOM_DEVICE;
         }
         EMOGI_HIP_TRY(cp(p.nextbits, p.snap_nextbits, words * 4), EMOGI_E_HIP);
+        EMOGI_HIP_TRY(cp(p.farbits, p.snap_farbits, words * 4), EMOGI_E_HIP);
     }
     return EMOGI_OK;
 }
@@ -1021,12 +1028,59 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             hipLaunchKernelGGL(k_iota, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
             EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
                           EMOGI_E_HIP);
-            if (g->col_bytes == 8)
+            const uint64_t davg = std::max<uint64_t>(1, g->E / V);
+            if (g->max_degree <= 4 * davg) {
+                // Lists of about equal length (no hubs): a read of each list's
+                // first ids costs one small host-link request per vertex, so
+                // instead hook the whole lists of the vertices in an id range
+                // that holds a fraction f of the edges (one sequential read).
+                // A vertex stays unhooked with probability (1-f)^(d+1) and is
+                // then read in full by step 3; f = ln(d+1)/(d+1) balances the two.
+                const double f = std::min(0.5, std::log(double(davg) + 1.0) / (double(davg) + 1.0));
+                const uint64_t target = uint64_t(f * double(g->E));
+                uint64_t lo = 0, hi = V;  // first vertex v1 with row_ptr[v1] >= target
+                while (lo < hi) {
+                    const uint64_t mid = lo + (hi - lo) / 2;
+                    uint64_t x = 0;
+                    EMOGI_HIP_TRY(hipMemcpy(&x, g->row_ptr + mid, sizeof(x), hipMemcpyDeviceToHost), EMOGI_E_HIP);
+                    if (x < target) lo = mid + 1; else hi = mid;
+                }
+                if (lo > 0) {
+                    if ((st = ensure_scan(g, V)) != EMOGI_OK) return st;
+                    ScanArgs s{};
+                    s.queue = nullptr;  // vertices 0 .. lo-1
+                    s.n = uint32_t(lo);
+                    s.n_dev = nullptr;
+                    s.row_ptr = g->row_ptr;
+                    s.col = g->col;
+                    s.align_mask = uint64_t(std::max<uint32_t>(1, g->request_unit / g->col_bytes)) - 1;
+                    s.req_unit = g->request_unit;
+                    s.col_bytes = g->col_bytes;
+                    s.tier = tier_view(g);
+                    const unsigned nb = unsigned((lo + kScanTile) / kScanTile);
+                    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums);
+                    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nb);
+                    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums,
+                                       p.chunk_scan);
+                    s.chunk_scan = p.chunk_scan;
+                    OpArgs a{};
+                    a.state = out;
+                    a.V = uint32_t(V);
+                    a.ctr = p.counters;
+                    a.split = 0xFFFFFFFFu;
+                    if (g->col_bytes == 8)
+                        launch_variant<uint64_t, A_LINK>(EMOGI_V5_BALANCED, s, a, stream);
+                    else
+                        launch_variant<uint32_t, A_LINK>(EMOGI_V5_BALANCED, s, a, stream);
+                }
+            } else if (g->col_bytes == 8) {
                 hipLaunchKernelGGL(k_cc_sample<uint64_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, g->row_ptr,
                                    static_cast<const uint64_t *>(g->col), V, tier_view(g), out, p.counters);
-            else
+            } else {
                 hipLaunchKernelGGL(k_cc_sample<uint32_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, g->row_ptr,
                                    static_cast<const uint32_t *>(g->col), V, tier_view(g), out, p.counters);
+            }
+            EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             hipLaunchKernelGGL(k_compress, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
             hipLaunchKernelGGL(k_cc_probe, dim3((kCcProbe + 255) / 256), dim3(256), 0, stream, out, V,
                                p.cc_probe);
@@ -1100,26 +1154,45 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             return EMOGI_E_OOM_DEVICE;
         }
         EMOGI_HIP_TRY(hipMemsetAsync(p.nextbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
+        if (algo == A_SSSP) {
+            if (!p.farbits && hipMalloc(&p.farbits, ((V + 31) / 32) * sizeof(uint32_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                p.farbits = nullptr;
+                set_error("hipMalloc of the SSSP band bitmap failed");
+                return EMOGI_E_OOM_DEVICE;
+            }
+            EMOGI_HIP_TRY(hipMemsetAsync(p.farbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
+        }
     }
     // SSSP distance bands (Sec. 5.1 leaves the SSSP algorithm open; this is a
-    // near-far worklist): a round expands the marked vertices whose distance is
-    // below `split`; when none is left the split moves to the smallest marked
-    // distance + delta.  delta = 0: one band, plain label correcting.
+    // near-far worklist): an improvement below `split` joins the next round
+    // (marked in nextbits), one at or above it waits (marked in farbits).
+    // When a round lists nothing, the split moves to the smallest waiting
+    // distance + delta and the waiting vertices below it are listed.
+    // delta = 0: one band, plain label correcting.
     const uint32_t delta = g->sssp_delta;
     uint32_t split = (algo == A_SSSP && delta > 0) ? delta : 0xFFFFFFFFu;
-    const uint32_t *band_dist = algo == A_SSSP ? out : nullptr;
     const uint64_t words = (V + 31) / 32;
     const unsigned nbw = unsigned((words + kBitsTile - 1) / kBitsTile);
-    // Lists the marks (below `cut` for SSSP) into `queue` in id order; the
-    // count lands in counters[C_NEXT], the smallest mark left in C_BANDMIN.
-    auto list_marks = [&](uint32_t *queue, uint32_t cut) {
-        hipLaunchKernelGGL(k_bits_count, dim3(nbw), dim3(kBlock), 0, stream, p.nextbits, words, band_dist, cut,
+    // Lists the marks in `bits` (with `dist`: those below `cut`) into `queue`
+    // in id order, also clearing them in `also_clear`; the count lands in
+    // counters[C_NEXT], the smallest distance left marked in C_BANDMIN.
+    auto list_marks = [&](uint32_t *bits, const uint32_t *dist, uint32_t cut, uint32_t *queue,
+                          uint32_t *also_clear) {
+        hipLaunchKernelGGL(k_bits_count, dim3(nbw), dim3(kBlock), 0, stream, bits, words, dist, cut,
                            p.block_sums, p.counters);
         hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nbw);
-        hipLaunchKernelGGL(k_bits_write, dim3(nbw), dim3(kBlock), 0, stream, p.nextbits, words, band_dist, cut,
-                           p.block_sums, nbw, queue, p.counters);
+        hipLaunchKernelGGL(k_bits_write, dim3(nbw), dim3(kBlock), 0, stream, bits, words, dist, cut,
+                           p.block_sums, nbw, queue, also_clear, p.counters);
     };
-    p.host_counters[C_BANDMIN] = 0;
+    auto sync_counters = [&]() -> emogi_status_t {
+        EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+        EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, stream),
+                      EMOGI_E_HIP);
+        EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+        return EMOGI_OK;
+    };
     // The scheduler's features and pick for the next frontier are computed
     // behind each level and come back with its counters (have_pick); the
     // first frontier, and one opened by an SSSP band step, is scored on its own.
@@ -1138,7 +1211,10 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     if (lb > 1) {
         if ((st = ensure_level_blocks(g, lb)) != EMOGI_OK) return st;
         const int m = g->sched_mode;
-        const int var = (m >= 0 && m < EMOGI_NUM_VARIANTS) ? m : heuristic_variant(g, V);
+        // without a fixed variant: a workgroup per vertex on small graphs (no
+        // prefix kernels per level; measured fastest on R-MAT 16 and 18), else V5
+        const int var = (m >= 0 && m < EMOGI_NUM_VARIANTS) ? m
+                        : g->E < (uint64_t(1) << 24) ? int(EMOGI_V4_BLOCK) : heuristic_variant(g, V);
         const unsigned nb_max = unsigned((V + kScanTile) / kScanTile);
         if (var == EMOGI_V5_BALANCED && (st = ensure_scan(g, V)) != EMOGI_OK) return st;
         while (n > 0) {
@@ -1172,6 +1248,8 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 a.V = uint32_t(V);
                 a.ctr = &p.level_ctr[i * C_COUNT];
                 a.nextbits = nullptr;
+                a.split = 0xFFFFFFFFu;
+                a.farbits = nullptr;
                 if (var == EMOGI_V5_BALANCED) {
                     const unsigned nb = i == 0 ? unsigned((n + kScanTile) / kScanTile) : nb_max;
                     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums);
@@ -1221,19 +1299,21 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     while (true) {
         if (n == 0) {
             // SSSP: the band is exhausted; open the next one at the smallest
-            // marked distance, or stop when nothing is marked
+            // waiting distance (a pass that lists nothing and keeps the
+            // minimum), or stop when nothing waits
             have_pick = false;
+            if (algo != A_SSSP || split == 0xFFFFFFFFu) break;
+            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
+            hipLaunchKernelGGL(k_bits_count, dim3(nbw), dim3(kBlock), 0, stream, p.farbits, words, out, 0u,
+                               p.block_sums, p.counters);
+            if ((st = sync_counters()) != EMOGI_OK) return st;
             const unsigned long long bm = p.host_counters[C_BANDMIN];
-            if (algo != A_SSSP || bm == 0) break;
+            if (bm == 0) break;
             const uint64_t m = 0x100000000ull - bm;
             split = uint32_t(std::min<uint64_t>(std::max<uint64_t>(m + delta, split), 0xFFFFFFFFull));
             EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
-            list_marks(p.queue[cur], split);
-            EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
-            EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
-                                         hipMemcpyDeviceToHost, stream),
-                          EMOGI_E_HIP);
-            EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+            list_marks(p.farbits, out, split, p.queue[cur], nullptr);
+            if ((st = sync_counters()) != EMOGI_OK) return st;
             n = p.host_counters[C_NEXT];
             continue;
         }
@@ -1267,6 +1347,8 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             a.V = uint32_t(V);
             a.ctr = p.counters;
             a.nextbits = ordered ? p.nextbits : nullptr;
+            a.split = split;
+            a.farbits = p.farbits;
             EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
                           EMOGI_E_HIP);
             if (v == EMOGI_V5_BALANCED) {
@@ -1294,7 +1376,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
             if (ordered) {
-                list_marks(s.next, split);
+                list_marks(p.nextbits, nullptr, 0xFFFFFFFFu, s.next, algo == A_SSSP ? p.farbits : nullptr);
                 EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             }
             if (prefetch) {
