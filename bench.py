@@ -344,7 +344,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         sched = {}
         modes = [("fixed_v3", 3), ("heuristic", "heuristic")]
         if os.path.exists(weights):
-            G.set_scheduler_weights(json.load(open(weights))["params"])
+            G.load_scheduler(weights)
             modes.append(("learned", "learned"))
         for name, mode in modes:
             if isinstance(mode, int):

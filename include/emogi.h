@@ -199,6 +199,10 @@ emogi_status_t emogi_set_cc_algorithm(emogi_graph_t g, int algorithm);
 /* Loads the 5638 fp32 scheduler parameters (order W1,b1,W2,b2,W3,b3, row-major)
  * from host memory; NULL clears them (learned mode then uses the heuristic). */
 emogi_status_t emogi_set_scheduler_weights(emogi_graph_t g, const float *params, size_t count);
+/* The feature range the network was trained on: lo[16] and hi[16] (host).
+ * A level whose features fall outside [lo, hi] in any component uses the
+ * heuristic instead of the network (no extrapolation).  Both NULL: no check. */
+emogi_status_t emogi_set_scheduler_range(emogi_graph_t g, const float *lo, const float *hi);
 
 /* ---- scheduler network training (16 -> 64 -> 64 -> 6, ReLU, softmax
  *      cross-entropy, Adam; fp32 HIP kernels).  The worker-size trade-off of

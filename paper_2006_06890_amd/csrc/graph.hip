@@ -138,6 +138,7 @@ static void release(emogi_graph_s *g) {
                     (void *)p.cc_probe, (void *)p.nextbits, (void *)p.farbits, (void *)p.snap_farbits})
         if (x) (void)hipFree(x);
     if (g->mlp_params) (void)hipFree(g->mlp_params);
+    if (g->mlp_range) (void)hipFree(g->mlp_range);
     tier_release(g);
     BatchPool &b = g->batch;
     for (int i = 0; i < 2; ++i) {

@@ -112,6 +112,7 @@ struct emogi_graph_s {
     int sched_mode = EMOGI_SCHED_HEURISTIC;
     bool record_features = false;  // store per-level frontier features in the stats
     float *mlp_params = nullptr;   // device, 5638 floats, or null
+    float *mlp_range = nullptr;    // device, 16 lower then 16 upper feature bounds, or null
     uint64_t max_degree = 0;
 
     emogi::Pool pool;

@@ -53,11 +53,14 @@ struct FeatureConsts {
 };
 
 // One wave: features from the histogram, then z = W3 relu(W2 relu(W1 x + b1) + b2) + b3,
-// argmax into *choice (-1 without weights).  Also stores the features for
-// harvesting, and clears the histogram for its next use.  n_dev as above.
+// argmax into *choice.  The choice is -1 without weights, or when a feature
+// lies outside the range the network was trained on (range: 16 lower, then
+// 16 upper bounds; null: no check), so the caller falls back to the
+// heuristic.  Also stores the features for harvesting, and clears the
+// histogram for its next use.  n_dev as above.
 __global__ __launch_bounds__(64) void k_mlp_pick(unsigned long long *acc, FeatureConsts c,
                                                  const unsigned long long *n_dev, const float *params,
-                                                 int *choice, float *feat_out) {
+                                                 const float *range, int *choice, float *feat_out) {
     __shared__ float x[kNIn], h1[kNH], h2[kNH], z[kNOut];
     const int t = threadIdx.x;
     if (n_dev) c.n = float(*n_dev);
@@ -76,6 +79,8 @@ __global__ __launch_bounds__(64) void k_mlp_pick(unsigned long long *acc, Featur
     __syncthreads();
     if (t < kHistBins + 1) acc[t] = 0;
     if (t < kNIn && feat_out) feat_out[t] = x[t];
+    const bool outside = range && t < kNIn && (x[t] < range[t] || x[t] > range[kNIn + t]);
+    if (__ballot(outside) != 0) params = nullptr;  // (uniform) no pick outside the trained range
     if (!params && t == 0) *choice = -1;
     const float *W1 = params, *b1 = W1 + kNH * kNIn, *W2 = b1 + kNH, *b2 = W2 + kNH * kNH,
                 *W3 = b2 + kNH, *b3 = W3 + kNOut * kNH;
@@ -151,7 +156,8 @@ static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *
     hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, n,
                        static_cast<const unsigned long long *>(nullptr), g->row_ptr, s.acc);
     hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(64), 0, stream, s.acc, feature_consts(g, algo, n),
-                       static_cast<const unsigned long long *>(nullptr), g->mlp_params, s.choice, s.feat);
+                       static_cast<const unsigned long long *>(nullptr), g->mlp_params, g->mlp_range, s.choice,
+                       s.feat);
     struct {
         int choice;
         float feat[kNIn];
@@ -163,7 +169,7 @@ static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *
         return -1;
     }
     if (features_host) memcpy(features_host, h.feat, sizeof(h.feat));
-    if (!g->mlp_params || h.choice < 0 || h.choice >= kNOut) return heuristic_variant(g, n);
+    if (!g->mlp_params || h.choice < 0 || h.choice >= kNOut) return heuristic_variant(g, n);  // also: outside range
     return h.choice;
 }
 
@@ -194,7 +200,7 @@ emogi_status_t sched_prefetch(emogi_graph_s *g, int algo, const uint32_t *queue,
     hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, uint64_t(0),
                        static_cast<const unsigned long long *>(&counters[C_NEXT]), g->row_ptr, s.acc);
     hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(64), 0, stream, s.acc, feature_consts(g, algo, 0),
-                       static_cast<const unsigned long long *>(&counters[C_NEXT]), g->mlp_params,
+                       static_cast<const unsigned long long *>(&counters[C_NEXT]), g->mlp_params, g->mlp_range,
                        reinterpret_cast<int *>(&counters[C_CHOICE]), reinterpret_cast<float *>(&counters[C_FEAT]));
     EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
     return EMOGI_OK;
@@ -258,6 +264,29 @@ emogi_status_t emogi_set_scheduler_weights(emogi_graph_t g, const float *params,
     }
     EMOGI_HIP_TRY(hipMemcpy(g->mlp_params, params, kNParams * sizeof(float), hipMemcpyHostToDevice),
                   EMOGI_E_HIP);
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_set_scheduler_range(emogi_graph_t g, const float *lo, const float *hi) {
+    if (!g || (!lo) != (!hi)) {
+        set_error("scheduler range needs both bounds or neither");
+        return EMOGI_E_INVALID;
+    }
+    if (!lo) {
+        if (g->mlp_range) (void)hipFree(g->mlp_range);
+        g->mlp_range = nullptr;
+        return EMOGI_OK;
+    }
+    if (!g->mlp_range) {
+        if (hipMalloc(&g->mlp_range, 2 * kNIn * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            g->mlp_range = nullptr;
+            set_error("hipMalloc for the scheduler range failed");
+            return EMOGI_E_OOM_DEVICE;
+        }
+    }
+    EMOGI_HIP_TRY(hipMemcpy(g->mlp_range, lo, kNIn * sizeof(float), hipMemcpyHostToDevice), EMOGI_E_HIP);
+    EMOGI_HIP_TRY(hipMemcpy(g->mlp_range + kNIn, hi, kNIn * sizeof(float), hipMemcpyHostToDevice), EMOGI_E_HIP);
     return EMOGI_OK;
 }
 

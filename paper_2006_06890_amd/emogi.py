@@ -193,6 +193,7 @@ def lib():
             "emogi_set_level_batch": (i32, [p, u32]),
             "emogi_set_frontier_order": (i32, [p, i32]),
             "emogi_set_scheduler_weights": (i32, [p, p, sz]),
+            "emogi_set_scheduler_range": (i32, [p, p, p]),
             "emogi_bfs": (i32, [p, u64, p, p]),
             "emogi_sssp": (i32, [p, u64, p, p]),
             "emogi_cc": (i32, [p, p, p]),
@@ -322,12 +323,29 @@ class Graph:
         m = modes[mode] if isinstance(mode, str) else int(mode)
         check(lib().emogi_set_scheduler(self._h, m | (SCHED_RECORD if record else 0)))
 
-    def set_scheduler_weights(self, params):
+    def set_scheduler_weights(self, params, feature_lo=None, feature_hi=None):
+        """Loads the network; with feature_lo/feature_hi (16 each) levels whose
+        features fall outside that training range use the heuristic."""
         if params is None:
             check(lib().emogi_set_scheduler_weights(self._h, None, 0))
+            check(lib().emogi_set_scheduler_range(self._h, None, None))
             return
         p = np.ascontiguousarray(params, dtype=np.float32)
         check(lib().emogi_set_scheduler_weights(self._h, p.ctypes.data, p.shape[0]))
+        if feature_lo is None:
+            check(lib().emogi_set_scheduler_range(self._h, None, None))
+        else:
+            lo = np.ascontiguousarray(feature_lo, dtype=np.float32)
+            hi = np.ascontiguousarray(feature_hi, dtype=np.float32)
+            if lo.shape != (16,) or hi.shape != (16,):
+                raise ValueError("feature bounds must have 16 entries each")
+            check(lib().emogi_set_scheduler_range(self._h, lo.ctypes.data, hi.ctypes.data))
+
+    def load_scheduler(self, path):
+        """Network and training feature range from a train_scheduler JSON file."""
+        import json
+        doc = json.load(open(path))
+        self.set_scheduler_weights(doc["params"], doc.get("feature_lo"), doc.get("feature_hi"))
 
     def set_frontier_order(self, ordered):
         """True: list each next frontier in ascending vertex id (bitmap compaction)."""

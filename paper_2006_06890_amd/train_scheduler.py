@@ -2,13 +2,16 @@
 
 1. Harvest: on training graphs shaped like the benchmark configurations
    (R-MAT scale 16 with 4-byte ids; R-MAT with 8-byte ids; uniform random with
-   4-byte ids; graph seeds 1, 2, 3), run BFS, SSSP and CC in probe mode: every
+   4-byte ids; scales up to 24; graph seeds 1, 2, 3), run BFS, SSSP and CC in
+   probe mode: every
    level is run with all six access variants on the same state, and the 16
    frontier features plus the six kernel times are kept.  The label of a level
    is its fastest variant.
 2. Train: the 16-64-64-6 network is trained on the GPU by the library's own
    HIP kernels (emogi_mlp_train: forward, softmax cross-entropy, backward,
-   Adam), from a seeded He-uniform initialisation.
+   Adam), from a seeded He-uniform initialisation.  The range of every
+   feature over the training levels is kept with the weights: outside it the
+   library uses the heuristic (the network is not extrapolated).
 3. Evaluate: on held-out locality-ordered power-law graphs (10^8 vertices,
    mean degree 36, exponent 2.1, runs of 1024; seeds 101-103),
    time each traversal with the fixed aligned-wave variant (the paper's
@@ -16,7 +19,8 @@
    per-level best (sum over levels of the fastest variant's probe time).
 
 Writes ``scheduler_weights.json`` next to this file:
-``{"params": [5638 floats], "train": {...}, "eval": {...}}``.
+``{"params": [5638 floats], "feature_lo": [16], "feature_hi": [16], "train": {...},
+"eval": {...}}``.
 
 Usage: python -m paper_2006_06890_amd.train_scheduler [--quick]
 """
@@ -96,14 +100,14 @@ def he_uniform(seed):
     return np.concatenate(parts).astype(np.float32)
 
 
-def evaluate(E, graphgen, specs, params, torch):
+def evaluate(E, graphgen, specs, params, torch, lo=None, hi=None):
     rows = []
     for spec in specs:
         g = _graph(E, graphgen, spec)
         out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
         srcs = _sources(g, 2, spec[3] + 5)
         with E.Graph(g.row_ptr, g.col, g.weights, placement="host_zero_copy", symmetric=True) as G:
-            G.set_scheduler_weights(params)
+            G.set_scheduler_weights(params, lo, hi)
             for algo in ("bfs", "sssp", "cc"):
                 res = {}
                 for mode in ("fixed_v3", "heuristic", "learned", "probe"):
@@ -160,13 +164,14 @@ def main():
         train_specs = []
         for seed in (1, 2, 3):
             train_specs += [("rmat", 16, 4, seed), ("rmat", 21, 8, seed), ("rmat", 22, 4, seed),
-                            ("uniform", 20, 4, seed), ("uniform", 22, 4, seed)]
+                            ("rmat", 24, 8, seed), ("uniform", 20, 4, seed), ("uniform", 22, 4, seed),
+                            ("uniform", 24, 4, seed)]
         eval_specs = [("powerlaw", args.eval_vertices, 4, s) for s in (101, 102, 103)]
 
     if args.eval_only:
         doc = json.load(open(args.eval_only))
         params = np.asarray(doc["params"], dtype=np.float32)
-        doc["eval"] = evaluate(E, graphgen, eval_specs, params, torch)
+        doc["eval"] = evaluate(E, graphgen, eval_specs, params, torch, doc.get("feature_lo"), doc.get("feature_hi"))
         json.dump(doc, open(args.out, "w"))
         log(f"wrote {args.out}")
         return
@@ -187,9 +192,13 @@ def main():
     params, hist = E.emogi.mlp_train(Xr, yr, p0, epochs=args.epochs, batch=min(256, Xr.shape[0]),
                                      lr=1e-3, seed=11)
     log(f"loss {hist[0]:.4f} -> {hist[-1]:.4f}")
-    rows = evaluate(E, graphgen, eval_specs, params, torch)
+    # the network is only trusted inside the feature range it was trained on
+    lo, hi = X.min(axis=0).astype(np.float32), X.max(axis=0).astype(np.float32)
+    rows = evaluate(E, graphgen, eval_specs, params, torch, lo, hi)
     json.dump({
         "params": [float(x) for x in params],
+        "feature_lo": [float(x) for x in lo],
+        "feature_hi": [float(x) for x in hi],
         "train": {"specs": train_specs, "levels": int(X.shape[0]),
                   "label_hist": np.bincount(y, minlength=6).tolist(),
                   "loss_first": float(hist[0]), "loss_last": float(hist[-1]),

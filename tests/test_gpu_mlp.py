@@ -132,6 +132,39 @@ def test_learned_picks_match_oracle_network(gpu_device):
         np.testing.assert_array_equal(E.to_u32(out), exp)
 
 
+def test_learned_scheduler_keeps_to_training_range(gpu_device):
+    """Levels whose features fall outside the trained range use the heuristic
+    (V5 for frontiers of 2048 or more, or hub graphs; V3 otherwise); inside
+    it the network's argmax is used."""
+    import torch
+    import paper_2006_06890_amd as E
+    g = graphgen.rmat(14, seed=3).to_csr(4, weights=True)
+    rng = np.random.Generator(np.random.PCG64(9))
+    theta = (rng.standard_normal(mlp.N_PARAMS) * 0.5).astype(np.float32)
+    out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+    s = int(np.argmax(g.degrees()))
+    hub = int(g.degrees().max()) > 4096
+    with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True) as G:
+        G.set_scheduler("learned", record=True)
+        # an empty range: every level falls back to the heuristic
+        G.set_scheduler_weights(theta, np.full(16, 2.0), np.full(16, -1.0))
+        for algo in ("bfs", "sssp"):
+            getattr(G, algo)(s, out)
+            st = G.stats()
+            heur = [5 if (n >= 2048 or hub) else 3 for n in st["level_frontier"]]
+            assert st["level_variant"] == heur, algo
+        # a range that holds every feature: the network decides
+        G.set_scheduler_weights(theta, np.full(16, -1e30), np.full(16, 1e30))
+        G.bfs(s, out)
+        st = G.stats()
+        F = np.array(st["level_features"], dtype=np.float64)
+        z, _ = mlp.forward(theta.astype(np.float64), F)
+        srt = np.sort(z, axis=1)
+        clear = (srt[:, -1] - srt[:, -2]) > 1e-3
+        assert np.array_equal(np.array(st["level_variant"])[clear], mlp.predict(theta.astype(np.float64), F)[clear])
+        np.testing.assert_array_equal(E.to_u32(out), oracle.bfs(g.row_ptr, g.col, s))
+
+
 def test_probe_mode_exact_and_times_every_variant(gpu_device):
     import torch
     import paper_2006_06890_amd as E

@@ -9,7 +9,6 @@ locality-ordered power-law graph times BFS, SSSP and CC with
 and reports the per-level best (probe mode) as the achievable bound.  Results
 must be identical to the oracle in every mode; the timings are printed.
 """
-import json
 import os
 
 import numpy as np
@@ -29,7 +28,6 @@ def test_learned_scheduler_gain(gpu_device):
     import paper_2006_06890_amd as E
     if not os.path.exists(WEIGHTS):
         pytest.skip("no trained scheduler weights committed")
-    params = np.array(json.load(open(WEIGHTS))["params"], dtype=np.float32)
     h = graphgen.power_law(1 << 20, seed=104)
     g = h.to_csr(4, weights=True)
     h.free()
@@ -40,7 +38,7 @@ def test_learned_scheduler_gain(gpu_device):
     out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
     rows = {}
     with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True) as G:
-        G.set_scheduler_weights(params)
+        G.load_scheduler(WEIGHTS)
         for mode in ("fixed_v3", "heuristic", "learned", "probe"):
             if mode == "fixed_v3":
                 G.set_variant(3)
