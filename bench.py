@@ -102,7 +102,9 @@ def kernel_key(algo, variant, col_bytes):
 
 
 KERNEL_SOURCES = ["paper_2006_06890_amd/csrc/traverse.hip", "paper_2006_06890_amd/csrc/wave.h",
-                  "paper_2006_06890_amd/csrc/internal.h"]
+                  "paper_2006_06890_amd/csrc/internal.h", "paper_2006_06890_amd/csrc/tier.h"]
+
+
 def counters_path(args):
     return os.path.join(ROOT, "profiles", f"counters_{args.config}_u{8 * args.col_bytes}.json")
 
@@ -295,7 +297,9 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             per[a]["edges"] += e
             per[a]["scan_ms"] += st["expand_ms"]
             per[a]["bytes"] += st["useful_link_bytes"]
-            eb = args.col_bytes + (4 if a == "sssp" else 0)
+            # algorithmic link bytes per edge of this run (SSSP reads a weight only
+            # where the edge can improve its target), spread over its levels
+            eb = st["useful_link_bytes"] / max(1, st["edges_scanned"])
             for v, ms, ed in zip(st["level_variant"], st["level_ms"], st["level_edges"]):
                 k = kernel_key(a, v, args.col_bytes)
                 kk = kernels.setdefault(k, {"ms": 0.0, "bytes": 0, "launches": 0})

@@ -93,10 +93,12 @@ typedef struct {
     uint32_t variant_hist[EMOGI_NUM_VARIANTS]; /* how many levels each variant ran     */
     uint64_t vertices_expanded;  /* frontier entries whose lists were scanned            */
     uint64_t edges_scanned;      /* sum of their out-degrees (re-expansions included)    */
-    uint64_t useful_link_bytes;  /* edges read over the host link * (col_bytes + 4 if
-                                    weights read): edges_scanned - tier_edges of them     */
+    uint64_t useful_link_bytes;  /* (edges_scanned - tier_edges) * col_bytes
+                                    + 4 * weights_read: bytes the lists need from the link */
     uint64_t request_bytes;      /* the same lists rounded out to the request unit R     */
     uint64_t tier_edges;         /* of edges_scanned, those read from the HBM tier       */
+    uint64_t weights_read;       /* SSSP: weights read over the host link (a weight is
+                                    read only when its edge could improve the target) */
     double total_ms;             /* whole traversal, HIP events on the caller's stream   */
     double expand_ms;            /* sum of the neighbour-scan kernels alone              */
     uint32_t expand_launches;    /* how many neighbour-scan kernels ran                  */

@@ -585,7 +585,8 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
     S.iterations = uint32_t(levels);
     S.edges_scanned = edges;
     S.tier_edges = b.host_ctr[B_TIER];
-    S.useful_link_bytes = (edges - S.tier_edges) * (g->col_bytes + (sssp ? 4u : 0u));
+    S.weights_read = sssp ? edges - S.tier_edges : 0;  // every weight of a scanned list
+    S.useful_link_bytes = (edges - S.tier_edges) * g->col_bytes + S.weights_read * 4;
     S.total_ms = ms;
     S.expand_ms = ms;
     S.expand_launches = uint32_t(steps);

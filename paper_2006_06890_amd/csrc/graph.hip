@@ -312,6 +312,22 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
     uint64_t maxd = 0;
     for (uint64_t u = 0; u < V; ++u) maxd = std::max(maxd, row_ptr[u + 1] - row_ptr[u]);
     g->max_degree = maxd;
+    // The smallest weight bounds what an edge can add to a distance: SSSP
+    // skips the weight read of an edge whose target is already that close.
+    g->min_weight = 0;
+    if (weights && E > 0) {
+        const unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+        std::vector<uint32_t> part(nt, 0xFFFFFFFFu);
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t] {
+                uint32_t m = 0xFFFFFFFFu;
+                for (uint64_t i = E * t / nt, end = E * (t + 1) / nt; i < end; ++i) m = std::min(m, weights[i]);
+                part[t] = m;
+            });
+        for (auto &x : th) x.join();
+        g->min_weight = *std::min_element(part.begin(), part.end());
+    }
 
     emogi_status_t st = EMOGI_OK;
     if (hipMalloc(&g->row_ptr, (V + 1) * sizeof(uint64_t)) != hipSuccess) {

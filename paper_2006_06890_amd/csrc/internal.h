@@ -35,7 +35,8 @@ enum Counter : int {
     C_CHOICE = 6,    // scheduler: variant picked for the next frontier (low 32 bits)
     C_FEAT = 7,      // scheduler: the next frontier's 16 features (fp32, 8 slots)
     C_TIER = 15,     // edges of expanded vertices whose lists were read from the HBM tier
-    C_COUNT = 16
+    C_WLINK = 16,    // SSSP: weights read over the host link
+    C_COUNT = 17
 };
 
 // HBM tier of neighbour lists (device arrays; see tier.h).
@@ -114,6 +115,7 @@ struct emogi_graph_s {
     float *mlp_params = nullptr;   // device, 5638 floats, or null
     float *mlp_range = nullptr;    // device, 16 lower then 16 upper feature bounds, or null
     uint64_t max_degree = 0;
+    uint32_t min_weight = 0;       // smallest edge weight (a bound for skipping weight reads)
 
     emogi::Pool pool;
     emogi::BatchPool batch;

@@ -40,17 +40,19 @@ constexpr int kMaxGrid = 256 * 8; // 8 blocks of 4 waves on each of the 256 CUs
 // End of a scan block: flush the staged frontier and fold the statistics.
 __device__ __forceinline__ void finish_block(Stage &st, uint32_t *next, unsigned long long *ctr,
                                              int lane, int wid, uint64_t edges, uint64_t reqb,
-                                             uint64_t verts, uint64_t tedges) {
+                                             uint64_t verts, uint64_t tedges, uint64_t wlink = 0) {
     finish_queue(st, next, &ctr[C_NEXT], lane, wid);
     edges = wave_sum64(edges);
     reqb = wave_sum64(reqb);
     verts = wave_sum64(verts);
     tedges = wave_sum64(tedges);
+    wlink = wave_sum64(wlink);
     if (lane == 0) {
         if (edges) atomicAdd(&ctr[C_EDGES], (unsigned long long)edges);
         if (reqb) atomicAdd(&ctr[C_REQBYTES], (unsigned long long)reqb);
         if (verts) atomicAdd(&ctr[C_VERTS], (unsigned long long)verts);
         if (tedges) atomicAdd(&ctr[C_TIER], (unsigned long long)tedges);
+        if (wlink) atomicAdd(&ctr[C_WLINK], (unsigned long long)wlink);
     }
 }
 
@@ -73,6 +75,7 @@ struct OpArgs {
                         // SSSP: vertices improved below the split this round
     uint32_t split;     // SSSP: improvements at or above it wait for a later band ...
     uint32_t *farbits;  // ... marked here
+    uint32_t wmin;      // SSSP: no edge weight is smaller
     unsigned long long *ctr;
 };
 
@@ -105,9 +108,11 @@ __device__ __forceinline__ void uf_link(uint32_t *parent, uint32_t a, uint32_t b
 }
 
 // Returns 1 when v joins the next frontier, 2 when an SSSP improvement waits
-// for a later band, else 0.
+// for a later band, else 0; SSSP adds kWeightRead when it read the weight.
+constexpr int kWeightRead = 4;
+
 template <int A>
-__device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v, uint32_t w) {
+__device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v, const uint32_t *wp) {
     if (v >= a.V) return 0;
     if (A == A_BFS) {
         // BFS: an unvisited neighbour is visited at the next level.
@@ -119,17 +124,22 @@ __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v,
         return 1;
     } else if (A == A_SSSP) {
         // SSSP: relax the edge; an improved vertex joins the next round when
-        // its distance is inside the band, otherwise it waits, marked.
-        uint64_t nd = uint64_t(uval) + w;
+        // its distance is inside the band, otherwise it waits, marked.  The
+        // weight is read (over the host link) only when the edge can improve
+        // v: with dist(v) <= dist(u) + the smallest weight it cannot.
+        const uint32_t cur = a.state[v];
+        const uint64_t floor_nd = uint64_t(uval) + a.wmin;
+        if (floor_nd <= 0xFFFFFFFEull && cur <= floor_nd) return 0;
+        const uint64_t nd = uint64_t(uval) + *wp;
         if (nd > 0xFFFFFFFEull) {
             atomicOr(&a.bitmap[v >> 5], 1u << (v & 31u));
             atomicOr(&a.ctr[C_OVERFLOW], 1ull);
-            return 0;
+            return kWeightRead;
         }
-        if (a.state[v] <= uint32_t(nd)) return 0;
+        if (cur <= uint32_t(nd)) return kWeightRead;
         uint32_t old = atomicMin(&a.state[v], uint32_t(nd));
-        if (old <= uint32_t(nd)) return 0;
-        return uint32_t(nd) < a.split ? 1 : 2;
+        if (old <= uint32_t(nd)) return kWeightRead;
+        return kWeightRead | (uint32_t(nd) < a.split ? 1 : 2);
     } else if (A == A_LINK) {
         uf_link(a.state, uval, v);
         return 0;
@@ -209,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s0, OpArgs a) {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(s.col);
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0;
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t q = uint64_t(blockIdx.x) * kWavesPerBlock + wid; q < s.n; q += nw) {
         const uint32_t u = uniform32(frontier_at(s, uint32_t(q)));
@@ -220,27 +230,26 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s0, OpArgs a) {
         if (lane == 0) count_list(src.tier, b, e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
         const uint64_t start = ALIGN ? (b & ~s.align_mask) : b;
         for (uint64_t j0 = start; j0 < e; j0 += uint64_t(kWave) * kUnroll) {
-            uint32_t v[kUnroll], w[kUnroll];
+            uint32_t v[kUnroll];
+            const uint32_t *wp[kUnroll];
             bool ok[kUnroll];
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
                 const uint64_t j = j0 + uint64_t(k) * kWave + lane;
                 ok[k] = (j >= b) && (j < e);
                 v[k] = 0;
-                w[k] = 0;
-                if (ok[k]) {
-                    v[k] = load_col(src.col, j - src.shift);
-                    if (A == A_SSSP) w[k] = src.w[j - src.shift];
-                }
+                wp[k] = (A == A_SSSP) ? src.w + (j - src.shift) : nullptr;
+                if (ok[k]) v[k] = load_col(src.col, j - src.shift);
             }
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
-                const int r = ok[k] ? visit<A>(a, uval, v[k], w[k]) : 0;
-                emit<A>(st, r, v[k], s.next, a, lane);
+                const int r = ok[k] ? visit<A>(a, uval, v[k], wp[k]) : 0;
+                if ((r & kWeightRead) && !src.tier) ++wlink;
+                emit<A>(st, r & 3, v[k], s.next, a, lane);
             }
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges);
+    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink);
 }
 
 // ---------------------------------------------------------------------------
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_block(ScanArgs s0, OpArgs a) {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(s.col);
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0;
     for (uint64_t q = blockIdx.x; q < s.n; q += gridDim.x) {
         const uint32_t u = uniform32(frontier_at(s, uint32_t(q)));
         const uint64_t b = uniform64(s.row_ptr[u]), e = uniform64(s.row_ptr[u + 1]);
@@ -263,27 +272,26 @@ __global__ __launch_bounds__(kBlock) void k_block(ScanArgs s0, OpArgs a) {
         if (lane == 0 && wid == 0) count_list(src.tier, b, e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
         const uint64_t start = b & ~s.align_mask;
         for (uint64_t j0 = start; j0 < e; j0 += uint64_t(kBlock) * 2) {
-            uint32_t v[2], w[2];
+            uint32_t v[2];
+            const uint32_t *wp[2];
             bool ok[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 const uint64_t j = j0 + uint64_t(k) * kBlock + uint64_t(wid) * kWave + lane;
                 ok[k] = (j >= b) && (j < e);
                 v[k] = 0;
-                w[k] = 0;
-                if (ok[k]) {
-                    v[k] = load_col(src.col, j - src.shift);
-                    if (A == A_SSSP) w[k] = src.w[j - src.shift];
-                }
+                wp[k] = (A == A_SSSP) ? src.w + (j - src.shift) : nullptr;
+                if (ok[k]) v[k] = load_col(src.col, j - src.shift);
             }
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                const int r = ok[k] ? visit<A>(a, uval, v[k], w[k]) : 0;
-                emit<A>(st, r, v[k], s.next, a, lane);
+                const int r = ok[k] ? visit<A>(a, uval, v[k], wp[k]) : 0;
+                if ((r & kWeightRead) && !src.tier) ++wlink;
+                emit<A>(st, r & 3, v[k], s.next, a, lane);
             }
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges);
+    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_group(ScanArgs s0, OpArgs a) {
     const ColT *col = static_cast<const ColT *>(s.col);
     constexpr int kGroups = kWave / G;
     const int g = lane / G, gl = lane % G;
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0;
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t q0 = (uint64_t(blockIdx.x) * kWavesPerBlock + wid) * kGroups; q0 < s.n;
          q0 += nw * kGroups) {
@@ -324,16 +332,14 @@ __global__ __launch_bounds__(kBlock) void k_group(ScanArgs s0, OpArgs a) {
         const uint64_t start = (G == 1) ? b : (b & ~uint64_t(G - 1));
         for (uint64_t j = start + gl; __ballot(j < e) != 0; j += G) {
             const bool ok = (j >= b) && (j < e);
-            uint32_t v = 0, w = 0;
-            if (ok) {
-                v = load_col(src.col, j - src.shift);
-                if (A == A_SSSP) w = src.w[j - src.shift];
-            }
-            const int r = ok ? visit<A>(a, uval, v, w) : 0;
-            emit<A>(st, r, v, s.next, a, lane);
+            uint32_t v = 0;
+            if (ok) v = load_col(src.col, j - src.shift);
+            const int r = ok ? visit<A>(a, uval, v, A == A_SSSP ? src.w + (j - src.shift) : nullptr) : 0;
+            if ((r & kWeightRead) && !src.tier) ++wlink;
+            emit<A>(st, r & 3, v, s.next, a, lane);
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges);
+    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink);
 }
 
 // ---------------------------------------------------------------------------
@@ -374,8 +380,9 @@ struct ChunkCursor {
 
 // kUnroll chunks' neighbours (and weights), loaded, not yet visited.
 struct ChunkGroup {
-    uint32_t v[kUnroll], w[kUnroll], uv[kUnroll];
-    bool ok[kUnroll];
+    uint32_t v[kUnroll], uv[kUnroll];
+    const uint32_t *wp[kUnroll];  // SSSP: where each lane's weight is (read only if needed)
+    bool ok[kUnroll], tier[kUnroll];
 };
 
 template <class ColT, int A>
@@ -412,7 +419,8 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
         const uint64_t kk = c.kb + i;
         g.ok[i] = false;
         g.v[i] = 0;
-        g.w[i] = 0;
+        g.wp[i] = nullptr;
+        g.tier[i] = false;
         g.uv[i] = c.uval;
         if (kk < c.kend) {
             while (kk >= c.qnext) {  // next entry that owns chunks (uniform)
@@ -426,10 +434,9 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
                 count_list(c.src.tier, c.b, c.e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
             const uint64_t j = (c.b & ~s.align_mask) + (kk - c.qfirst) * kWave + lane;
             g.ok[i] = (j >= c.b) && (j < c.e);
-            if (g.ok[i]) {
-                g.v[i] = load_col(c.src.col, j - c.src.shift);
-                if (A == A_SSSP) g.w[i] = c.src.w[j - c.src.shift];
-            }
+            if (A == A_SSSP) g.wp[i] = c.src.w + (j - c.src.shift);
+            g.tier[i] = c.src.tier;
+            if (g.ok[i]) g.v[i] = load_col(c.src.col, j - c.src.shift);
         }
     }
     c.kb += kUnroll;
@@ -445,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s0, OpArgs a) {
     __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0;
     ChunkCursor<ColT> c;
     c.total = s.chunk_scan[s.n];
     c.stride = uint64_t(gridDim.x) * kWavesPerBlock * kChunksPerWave;
@@ -455,11 +462,12 @@ __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s0, OpArgs a) {
         load_group<ColT, A>(c, g, s, a, lane, edges, reqb, verts, tedges);
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i) {
-            const int r = g.ok[i] ? visit<A>(a, g.uv[i], g.v[i], g.w[i]) : 0;
-            emit<A>(st, r, g.v[i], s.next, a, lane);
+            const int r = g.ok[i] ? visit<A>(a, g.uv[i], g.v[i], g.wp[i]) : 0;
+            if ((r & kWeightRead) && !g.tier[i]) ++wlink;
+            emit<A>(st, r & 3, g.v[i], s.next, a, lane);
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges);
+    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink);
 }
 
 // ---------------------------------------------------------------------------
@@ -1250,6 +1258,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 a.nextbits = nullptr;
                 a.split = 0xFFFFFFFFu;
                 a.farbits = nullptr;
+                a.wmin = 0;
                 if (var == EMOGI_V5_BALANCED) {
                     const unsigned nb = i == 0 ? unsigned((n + kScanTile) / kScanTile) : nb_max;
                     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums);
@@ -1349,6 +1358,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             a.nextbits = ordered ? p.nextbits : nullptr;
             a.split = split;
             a.farbits = p.farbits;
+            a.wmin = g->min_weight;
             EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
                           EMOGI_E_HIP);
             if (v == EMOGI_V5_BALANCED) {
@@ -1433,6 +1443,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         S.tier_edges += hc[C_TIER];
         S.request_bytes += hc[C_REQBYTES];
         S.vertices_expanded += hc[C_VERTS];
+        S.weights_read += hc[C_WLINK];
         if (hc[C_OVERFLOW]) overflow_seen = true;
         n = hc[C_NEXT];
         if (identity) {
@@ -1446,7 +1457,8 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     if (kalgo == A_LINK)
         hipLaunchKernelGGL(k_compress, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
     S.iterations = iter;
-    S.useful_link_bytes = (S.edges_scanned - S.tier_edges) * (g->col_bytes + (algo == A_SSSP ? 4u : 0u));
+    // ids of every list read over the link; SSSP weights only where read
+    S.useful_link_bytes = (S.edges_scanned - S.tier_edges) * g->col_bytes + S.weights_read * 4;
     if (overflow_seen) {
         EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
                       EMOGI_E_HIP);

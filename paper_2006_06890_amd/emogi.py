@@ -42,6 +42,7 @@ class Stats(ctypes.Structure):
         ("useful_link_bytes", ctypes.c_uint64),
         ("request_bytes", ctypes.c_uint64),
         ("tier_edges", ctypes.c_uint64),
+        ("weights_read", ctypes.c_uint64),
         ("total_ms", ctypes.c_double),
         ("expand_ms", ctypes.c_double),
         ("expand_launches", ctypes.c_uint32),
@@ -65,6 +66,7 @@ class Stats(ctypes.Structure):
             "useful_link_bytes": self.useful_link_bytes,
             "request_bytes": self.request_bytes,
             "tier_edges": self.tier_edges,
+            "weights_read": self.weights_read,
             "total_ms": self.total_ms,
             "expand_ms": self.expand_ms,
             "expand_launches": self.expand_launches,

@@ -211,6 +211,40 @@ def test_ordered_frontier(gpu_device, name):
         _run_all(E, g, G, f"ordered-nodelta/{name}", algos=("sssp",), variants=[3, 5])
 
 
+@pytest.mark.parametrize("wkind", ["zero", "constant", "heavy"])
+def test_sssp_weight_skipping_bounds(gpu_device, wkind):
+    """A weight is read only when its edge could improve the target, judged
+    with the graph's smallest weight: weights that include 0, one constant
+    weight, and large weights all give Dijkstra's distances, and a star's
+    centre reads every weight."""
+    import torch
+    E = _emogi()
+    for name in ("rmat13", "uniform11", "star5000", "path300"):
+        g = graphs()[name]
+        rng = np.random.Generator(np.random.PCG64(3))
+        if wkind == "zero":
+            w = rng.integers(0, 4, size=g.num_edges).astype(np.uint32)
+        elif wkind == "constant":
+            w = np.full(g.num_edges, 7, dtype=np.uint32)
+        else:
+            w = rng.integers(1 << 20, 1 << 22, size=g.num_edges).astype(np.uint32)
+        out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+        with E.Graph(g.row_ptr, g.col, w, symmetric=(wkind != "zero")) as G:
+            for v in (0, 3, 5):
+                G.set_variant(v)
+                for s in _sources(g):
+                    G.sssp(s, out)
+                    np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(g.row_ptr, g.col, w, s),
+                                                  err_msg=f"{name} {wkind} V{v} s{s}")
+                    st = G.stats()
+                    assert st["weights_read"] <= st["edges_scanned"]
+                    assert st["useful_link_bytes"] == st["edges_scanned"] * 4 + st["weights_read"] * 4
+        if name == "star5000":
+            with E.Graph(g.row_ptr, g.col, w) as G:
+                G.sssp(0, out)
+                assert G.stats()["weights_read"] == g.num_edges // 2  # every leaf improves once
+
+
 def test_directed_sssp_delta(gpu_device):
     import torch
     E = _emogi()
@@ -274,6 +308,7 @@ def test_sssp_unit_band_expands_each_vertex_once(gpu_device, name):
             st = G.stats()
             fin = exp != E.INF
             assert st["edges_scanned"] == int(deg[fin].sum()), (s, st["edges_scanned"])
+            assert 0 < st["weights_read"] <= st["edges_scanned"] or st["edges_scanned"] == 0
             assert st["vertices_expanded"] == int((fin & (deg > 0)).sum())
             assert st["iterations"] == np.unique(exp[fin]).shape[0]
 
