@@ -380,9 +380,13 @@ struct ChunkCursor {
 
 // kUnroll chunks' neighbours (and weights), loaded, not yet visited.
 struct ChunkGroup {
-    uint32_t v[kUnroll], uv[kUnroll];
-    const uint32_t *wp[kUnroll];  // SSSP: where each lane's weight is (read only if needed)
-    bool ok[kUnroll], tier[kUnroll];
+    uint32_t v[kUnroll];
+    bool ok[kUnroll];
+    // wave-uniform per chunk: the source value, where lane 0's weight is
+    // (SSSP reads lane l's at wbase + l only if needed), and the tier flag
+    uint32_t uv[kUnroll];
+    uint64_t wbase[kUnroll];
+    bool tier[kUnroll];
 };
 
 template <class ColT, int A>
@@ -419,7 +423,7 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
         const uint64_t kk = c.kb + i;
         g.ok[i] = false;
         g.v[i] = 0;
-        g.wp[i] = nullptr;
+        g.wbase[i] = 0;
         g.tier[i] = false;
         g.uv[i] = c.uval;
         if (kk < c.kend) {
@@ -432,9 +436,10 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
             g.uv[i] = c.uval;
             if (kk == c.qfirst && lane == 0)
                 count_list(c.src.tier, c.b, c.e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
-            const uint64_t j = (c.b & ~s.align_mask) + (kk - c.qfirst) * kWave + lane;
+            const uint64_t j0 = uniform64((c.b & ~s.align_mask) + (kk - c.qfirst) * kWave);
+            const uint64_t j = j0 + lane;
             g.ok[i] = (j >= c.b) && (j < c.e);
-            if (A == A_SSSP) g.wp[i] = c.src.w + (j - c.src.shift);
+            if (A == A_SSSP) g.wbase[i] = uniform64(reinterpret_cast<uint64_t>(c.src.w + (j0 - c.src.shift)));
             g.tier[i] = c.src.tier;
             if (g.ok[i]) g.v[i] = load_col(c.src.col, j - c.src.shift);
         }
@@ -447,7 +452,8 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
 // the next group's loads in flight during the visits measured no faster:
 // vector loads return in issue order, so the visits' HBM loads wait for them.)
 template <class ColT, int A>
-__global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s0, OpArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_balanced(ScanArgs s0,
+                                                                                           OpArgs a) {
     const ScanArgs s = resolved(s0);
     __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
@@ -462,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_balanced(ScanArgs s0, OpArgs a) {
         load_group<ColT, A>(c, g, s, a, lane, edges, reqb, verts, tedges);
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i) {
-            const int r = g.ok[i] ? visit<A>(a, g.uv[i], g.v[i], g.wp[i]) : 0;
+            const int r = g.ok[i] ? visit<A>(a, g.uv[i], g.v[i], reinterpret_cast<const uint32_t *>(g.wbase[i]) + lane) : 0;
             if ((r & kWeightRead) && !g.tier[i]) ++wlink;
             emit<A>(st, r & 3, g.v[i], s.next, a, lane);
         }
@@ -1231,10 +1237,11 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 set_error("iteration cap %llu reached", (unsigned long long)cap);
                 return EMOGI_E_NOCONVERGE;
             }
-            EMOGI_HIP_TRY(hipMemsetAsync(p.level_ctr, 0, size_t(lb) * C_COUNT * sizeof(unsigned long long), stream),
+            const uint32_t k = uint32_t(std::min<uint64_t>(lb, cap - iter));  // the cap holds exactly
+            EMOGI_HIP_TRY(hipMemsetAsync(p.level_ctr, 0, size_t(k) * C_COUNT * sizeof(unsigned long long), stream),
                           EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
-            for (uint32_t i = 0; i < lb; ++i) {
+            for (uint32_t i = 0; i < k; ++i) {
                 ScanArgs s;
                 s.queue = p.queue[cur];
                 s.n = i == 0 ? uint32_t(n) : uint32_t(V);  // later levels: V only sizes the grids
@@ -1275,7 +1282,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             }
             EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
-            EMOGI_HIP_TRY(hipMemcpyAsync(p.level_host, p.level_ctr, size_t(lb) * C_COUNT * sizeof(unsigned long long),
+            EMOGI_HIP_TRY(hipMemcpyAsync(p.level_host, p.level_ctr, size_t(k) * C_COUNT * sizeof(unsigned long long),
                                          hipMemcpyDeviceToHost, stream),
                           EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
@@ -1283,7 +1290,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             EMOGI_HIP_TRY(hipEventElapsedTime(&ms, g->ev_k0, g->ev_k1), EMOGI_E_HIP);
             S.expand_ms += ms;
             uint32_t ran = 0;
-            for (uint32_t i = 0; i < lb && n > 0; ++i, ++ran) {
+            for (uint32_t i = 0; i < k && n > 0; ++i, ++ran) {
                 const unsigned long long *hc = &p.level_host[i * C_COUNT];
                 if (iter < EMOGI_MAX_LEVEL_STATS) {
                     S.level_variant[iter] = uint8_t(var);
