@@ -279,6 +279,13 @@ typedef struct {
     uint32_t steps_per_graph; /* level steps per hipGraph replay (even, 2..32)             */
     uint32_t blocks_per_cu;   /* grid = 256 * blocks_per_cu workgroups (1..8)             */
     uint32_t use_graph;       /* 1: capture + replay hipGraphs, 0: launch steps directly   */
+    uint32_t sssp_delta;      /* SSSP distance band shared by the batch's sources.  0: one
+                                 band, every improvement expanded in the next step.  d > 0:
+                                 a source whose distance at a vertex is not below the split
+                                 waits there (one bit per vertex and source); when a step
+                                 expands nothing the split moves to the smallest waiting
+                                 distance + d and the waiting sources below it are listed
+                                 (one pass over V).  Results do not depend on d.           */
 } emogi_batch_params_t;
 
 emogi_status_t emogi_bfs_batch(emogi_graph_t g, const uint64_t *srcs, uint32_t n, uint32_t *out,

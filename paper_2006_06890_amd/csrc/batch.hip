@@ -31,7 +31,11 @@ enum BatchCounter : int {
     B_OVF = 5,           // SSSP: an overflowing relaxation happened / a distance overflowed
     B_EDGES = 6,         // sum of degrees of expanded vertices
     B_TIER = 7,          // of those, edges read from the HBM tier
-    B_COUNT = 8
+    B_READY = 8,         // SSSP bands: 1 when this step expanded a vertex (some source inside the band)
+    B_BMIN = 9,          // SSSP: 2^32 - smallest distance left pending beyond the band (0: none)
+    B_SPLIT = 10,        // SSSP: the band's upper end, shared by all sources
+    B_REFILL = 11,       // SSSP: 1 when the next step starts by listing waiting sources
+    B_COUNT = 12
 };
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
@@ -44,6 +48,7 @@ struct BatchArgs {
     unsigned long long *front, *next;  // masks: current and next frontier
     unsigned long long *vis;           // BFS
     unsigned long long *ovf;           // SSSP
+    unsigned long long *wait;          // SSSP: sources waiting for a later band, per vertex
     uint32_t *out;                     // BFS: levels [n][V]; SSSP: dist [V][64]
     const uint32_t *q, *h;             // current short / hub queues
     uint32_t *nq, *nh;                 // next short / hub queues
@@ -54,7 +59,9 @@ struct BatchArgs {
     uint64_t align_mask;
     uint32_t hub_degree;
     TierView tier;                     // HBM copies of hub lists (tier.bits null: none)
+    uint32_t delta;                    // SSSP band width (0: one band)
 };
+
 
 // Folds a kernel's expanded-edge counts into the batch counters.
 __device__ __forceinline__ void batch_count(const BatchArgs &a, int lane, uint64_t edges, uint64_t tedges) {
@@ -74,6 +81,79 @@ __device__ __forceinline__ void push_vertex(const BatchArgs &a, Stage &st, bool 
         const uint32_t i = uint32_t(atomicAdd(&a.ctr[B_H0 + (a.cur ^ 1)], 1ull));
         a.nh[i] = v;
     }
+}
+
+// SSSP bands for a batch: a source whose distance at u is not below the
+// shared split waits — its bit moves to wait[u] and u is not re-queued for
+// it; the smallest waiting distance decides the next split when a step finds
+// nothing inside the band (the next step then lists the waiting sources that
+// the new band covers, k_brefill).  Returns the mask of sources ready to
+// expand u.  Uniform per wave; `lead` marks the one wave (of a workgroup)
+// that records the waits.
+__device__ __forceinline__ unsigned long long sssp_ready(const BatchArgs &a, uint32_t u, unsigned long long fm,
+                                                         uint32_t du, int lane, bool lead) {
+    if (!a.delta) return fm;  // one band: every pending source expands
+    const uint32_t split = uint32_t(a.ctr[B_SPLIT]);
+    const bool pend = (fm >> lane) & 1ull;
+    const unsigned long long rm = __ballot(pend && du < split);
+    const unsigned long long wait = fm & ~rm;
+    if (wait && lead) {
+        uint32_t m = (pend && du >= split) ? du : kInf;
+        for (int o = 32; o > 0; o >>= 1) m = min(m, uint32_t(__shfl_xor(m, o)));
+        if (lane == 0) {
+            atomicMax(&a.ctr[B_BMIN], 0x100000000ull - m);
+            atomicOr(&a.wait[u], wait);
+        }
+    }
+    if (rm && lead && lane == 0) {
+        a.ctr[B_READY] = 1ull;
+        if (a.wait[u] & rm) atomicAnd(&a.wait[u], ~rm);  // expanded now: no longer waiting
+    }
+    return rm;
+}
+
+// First kernel of every SSSP step: after a band change (ctr[B_REFILL]) the
+// waiting sources now below the split join the current frontier masks and
+// their vertices the current queues; the sources still waiting give the
+// smallest waiting distance again.  Does nothing otherwise.
+__global__ __launch_bounds__(kBlock) void k_brefill(BatchArgs a) {
+    if (a.ctr[B_REFILL] == 0) return;
+    __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    Stage st{seg[wid], 0};
+    const uint32_t split = uint32_t(a.ctr[B_SPLIT]);
+    uint32_t *q = const_cast<uint32_t *>(a.q);
+    uint32_t m = kInf;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t v0 = uint64_t(blockIdx.x) * blockDim.x + uint64_t(wid) * kWave; v0 < a.V; v0 += stride) {
+        const uint64_t mine = v0 + lane;
+        const unsigned long long wv = mine < a.V ? a.wait[mine] : 0ull;
+        for (unsigned long long todo = __ballot(wv != 0ull); todo; todo &= todo - 1) {
+            const int k = __builtin_ctzll(todo);
+            const uint32_t u = uint32_t(v0 + k);
+            const unsigned long long wu = uniform64(__shfl(wv, k));
+            const bool w8 = (wu >> lane) & 1ull;
+            const uint32_t du = w8 ? a.out[uint64_t(u) * 64 + lane] : kInf;
+            const unsigned long long rm = __ballot(w8 && du < split);
+            if (w8 && du >= split) m = min(m, du);
+            bool push = false, hub = false;
+            if (rm && lane == 0) {
+                atomicAnd(&a.wait[u], ~rm);
+                push = atomicOr(const_cast<unsigned long long *>(&a.front[u]), rm) == 0ull;
+                hub = (a.row_ptr[u + 1] - a.row_ptr[u]) > a.hub_degree;
+            }
+            push = __shfl(int(push), 0) != 0;
+            hub = __shfl(int(hub), 0) != 0;
+            stage(st, push && !hub && lane == 0, u, q, &a.ctr[B_Q0 + a.cur], lane);
+            if (push && hub && lane == 0) {
+                const uint32_t i = uint32_t(atomicAdd(&a.ctr[B_H0 + a.cur], 1ull));
+                const_cast<uint32_t *>(a.h)[i] = u;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) m = min(m, uint32_t(__shfl_xor(m, o)));
+    if (lane == 0 && m != kInf) atomicMax(&a.ctr[B_BMIN], 0x100000000ull - m);
+    finish_queue(st, q, &a.ctr[B_Q0 + a.cur], lane, wid);
 }
 
 // BFS step for one neighbour v of a vertex whose frontier mask is fm.
@@ -237,8 +317,9 @@ __global__ __launch_bounds__(kBlock) void k_bsssp_short(BatchArgs a) {
     for (uint64_t q = uint64_t(blockIdx.x) * kWavesPerBlock + wid; q < n; q += nw) {
         const uint32_t u = uniform32(a.q[q]);
         const uint64_t b = uniform64(a.row_ptr[u]), e = uniform64(a.row_ptr[u + 1]);
-        const unsigned long long fm = uniform64(a.front[u]);
         const uint32_t du = a.out[uint64_t(u) * 64 + lane];
+        const unsigned long long fm = sssp_ready(a, u, uniform64(a.front[u]), du, lane, true);
+        if (!fm) continue;
         const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
         if (lane == 0) {
             edges += e - b;
@@ -267,8 +348,9 @@ __global__ __launch_bounds__(kBlock) void k_bsssp_hub(BatchArgs a) {
     for (uint64_t q = blockIdx.x; q < n; q += gridDim.x) {
         const uint32_t u = uniform32(a.h[q]);
         const uint64_t b = uniform64(a.row_ptr[u]), e = uniform64(a.row_ptr[u + 1]);
-        const unsigned long long fm = uniform64(a.front[u]);
         const uint32_t du = a.out[uint64_t(u) * 64 + lane];
+        const unsigned long long fm = sssp_ready(a, u, uniform64(a.front[u]), du, lane, wid == 0);
+        if (!fm) continue;
         const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
         if (lane == 0 && wid == 0) {
             edges += e - b;
@@ -297,9 +379,26 @@ __global__ __launch_bounds__(kBlock) void k_bclear(BatchArgs a) {
     }
 }
 
-__global__ void k_btick(unsigned long long *ctr, int cur) {
+// End of a step.  BFS, and SSSP in one band: a step with a non-empty queue is
+// a level / round.  SSSP in bands: a step that expanded something is a round;
+// one that only deferred sources opens the next band at the smallest waiting
+// distance + delta and has the next step list the waiting sources first.
+__global__ void k_btick(unsigned long long *ctr, int cur, int sssp, uint32_t delta) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        if (ctr[B_Q0 + cur] + ctr[B_H0 + cur] > 0) ctr[B_LEVEL] += 1;
+        if (!sssp || !delta) {
+            if (ctr[B_Q0 + cur] + ctr[B_H0 + cur] > 0) ctr[B_LEVEL] += 1;
+        } else {
+            ctr[B_REFILL] = 0;  // consumed by this step's k_brefill
+            if (ctr[B_READY] > 0) {
+                ctr[B_LEVEL] += 1;
+            } else if (delta && ctr[B_BMIN] != 0) {
+                const unsigned long long next = (0x100000000ull - ctr[B_BMIN]) + delta;
+                ctr[B_SPLIT] = next < 0xFFFFFFFFull ? next : 0xFFFFFFFFull;
+                ctr[B_REFILL] = 1;
+                ctr[B_BMIN] = 0;  // k_brefill recomputes it for the sources left waiting
+            }
+        }
+        ctr[B_READY] = 0;
         ctr[B_Q0 + cur] = 0;
         ctr[B_H0 + cur] = 0;
     }
@@ -323,7 +422,10 @@ __global__ void k_bseed(BatchArgs a, const uint64_t *srcs, int sssp) {
     if (blockIdx.x != 0 || s >= a.n) return;
     const uint32_t v = uint32_t(srcs[s]);
     const unsigned long long bit = 1ull << s;
-    if (sssp) a.out[uint64_t(v) * 64 + s] = 0;
+    if (sssp) {
+        a.out[uint64_t(v) * 64 + s] = 0;
+        if (s == 0) a.ctr[B_SPLIT] = a.delta ? a.delta : kInf;
+    }
     else {
         a.out[uint64_t(s) * a.V + v] = 0;
         atomicOr(&a.vis[v], bit);
@@ -394,6 +496,7 @@ static emogi_status_t ensure_batch(emogi_graph_s *g, bool sssp) {
     if ((st = dalloc(reinterpret_cast<void **>(&b.srcs), 64 * 8)) != EMOGI_OK) return st;
     if (sssp) {
         if ((st = dalloc(reinterpret_cast<void **>(&b.ovf), V * 8)) != EMOGI_OK) return st;
+        if ((st = dalloc(reinterpret_cast<void **>(&b.wait), V * 8)) != EMOGI_OK) return st;
         if ((st = dalloc(reinterpret_cast<void **>(&b.dist), V * 64 * 4)) != EMOGI_OK) return st;
     } else {
         if ((st = dalloc(reinterpret_cast<void **>(&b.vis), V * 8)) != EMOGI_OK) return st;
@@ -417,6 +520,7 @@ static emogi_status_t ensure_batch(emogi_graph_s *g, bool sssp) {
 template <class ColT>
 static void launch_step(const BatchArgs &a, bool sssp, unsigned grid, hipStream_t s) {
     if (sssp) {
+        if (a.delta) hipLaunchKernelGGL(k_brefill, dim3(grid), dim3(kBlock), 0, s, a);
         hipLaunchKernelGGL(k_bsssp_short<ColT>, dim3(grid), dim3(kBlock), 0, s, a);
         hipLaunchKernelGGL(k_bsssp_hub<ColT>, dim3(grid), dim3(kBlock), 0, s, a);
     } else {
@@ -424,7 +528,7 @@ static void launch_step(const BatchArgs &a, bool sssp, unsigned grid, hipStream_
         hipLaunchKernelGGL(k_bbfs_hub<ColT>, dim3(grid), dim3(kBlock), 0, s, a);
     }
     hipLaunchKernelGGL(k_bclear, dim3(grid), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_btick, dim3(1), dim3(64), 0, s, a.ctr, a.cur);
+    hipLaunchKernelGGL(k_btick, dim3(1), dim3(64), 0, s, a.ctr, a.cur, sssp ? 1 : 0, a.delta);
 }
 
 static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *srcs, uint32_t n,
@@ -465,6 +569,7 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
     a.w = g->weights;
     a.vis = b.vis;
     a.ovf = b.ovf;
+    a.wait = b.wait;
     a.out = sssp ? b.dist : out;
     a.ctr = b.ctr;
     a.n = n;
@@ -472,6 +577,7 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
     a.align_mask = std::max<uint32_t>(1, g->request_unit / g->col_bytes) - 1;
     a.tier = tier_view(g);
     a.hub_degree = P.hub_degree;
+    a.delta = sssp ? P.sssp_delta : 0;
     // ---- init ----
     EMOGI_HIP_TRY(hipMemcpyAsync(b.srcs, srcs, n * sizeof(uint64_t), hipMemcpyHostToDevice, s), EMOGI_E_HIP);
     hipLaunchKernelGGL(k_bfill64, dim3(grid_for(B_COUNT)), dim3(256), 0, s, b.ctr, uint64_t(B_COUNT));
@@ -479,6 +585,7 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
         hipLaunchKernelGGL(k_bfill64, dim3(grid_for(V)), dim3(256), 0, s, b.mask[i], V);
     if (sssp) {
         hipLaunchKernelGGL(k_bfill64, dim3(grid_for(V)), dim3(256), 0, s, b.ovf, V);
+        hipLaunchKernelGGL(k_bfill64, dim3(grid_for(V)), dim3(256), 0, s, b.wait, V);
         hipLaunchKernelGGL(k_bfill32, dim3(grid_for(V * 64)), dim3(256), 0, s, b.dist, V * 64, kInf);
     } else {
         hipLaunchKernelGGL(k_bfill64, dim3(grid_for(V)), dim3(256), 0, s, b.vis, V);
@@ -534,7 +641,9 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
             return EMOGI_E_HIP;
         }
     }
-    uint64_t cap = V + 2;
+    // rounds: each expands at least one vertex for one source, and with
+    // bands the sources' rounds interleave, so the bound scales with n
+    uint64_t cap = (V + 2) * (sssp ? n : 1);
     if (const char *env = getenv("EMOGI_MAX_ITERS")) cap = std::min<uint64_t>(cap, strtoull(env, nullptr, 10));
     uint64_t steps = 0;
     emogi_status_t rc = EMOGI_OK;
@@ -557,8 +666,12 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
             rc = EMOGI_E_HIP;
             break;
         }
-        if (b.host_ctr[B_Q0] + b.host_ctr[B_H0] == 0) break;  // K is even: parity 0 is current
-        if (steps >= cap) {
+        // K is even: parity 0 is current; SSSP is done when nothing waits either
+        if (b.host_ctr[B_Q0] + b.host_ctr[B_H0] == 0 && b.host_ctr[B_REFILL] == 0 && b.host_ctr[B_BMIN] == 0) break;
+        // a step that expands nothing opens a band; its listing step finds
+        // the smallest waiting distance anew, so at most two such steps come
+        // in a row and steps stay below three times the rounds
+        if (b.host_ctr[B_LEVEL] >= cap || steps >= 3 * cap + K) {
             set_error("iteration cap %llu reached", (unsigned long long)cap);
             rc = EMOGI_E_NOCONVERGE;
             break;
@@ -650,7 +763,7 @@ emogi_status_t emogi_autotune_batch(emogi_graph_t g, int algo, const uint64_t *s
     for (uint32_t h : hubs)
         for (uint32_t k : ks)
             for (uint32_t c : bpc) {
-                g->batch_params = emogi_batch_params_t{h, k, c, 1};
+                g->batch_params = emogi_batch_params_t{h, k, c, 1, keep.sssp_delta};
                 emogi_status_t st = run_batch(g, algo == 1, srcs, n, out, static_cast<hipStream_t>(stream));
                 if (st != EMOGI_OK) {
                     g->batch_params = keep;

@@ -145,7 +145,7 @@ static void release(emogi_graph_s *g) {
         if (b.mask[i]) (void)hipFree(b.mask[i]);
         if (b.hub[i]) (void)hipFree(b.hub[i]);
     }
-    for (void *x : {(void *)b.vis, (void *)b.ovf, (void *)b.dist, (void *)b.ctr, (void *)b.srcs})
+    for (void *x : {(void *)b.vis, (void *)b.ovf, (void *)b.wait, (void *)b.dist, (void *)b.ctr, (void *)b.srcs})
         if (x) (void)hipFree(x);
     if (b.host_ctr) (void)hipHostFree(b.host_ctr);
     if (b.stream) (void)hipStreamDestroy(b.stream);

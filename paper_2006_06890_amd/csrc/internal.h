@@ -82,6 +82,7 @@ struct BatchPool {
     unsigned long long *mask[2] = {nullptr, nullptr}; // frontier masks (current / next) per vertex
     unsigned long long *vis = nullptr;    // BFS: sources that reached v
     unsigned long long *ovf = nullptr;    // SSSP: sources whose relaxation into v overflowed
+    unsigned long long *wait = nullptr;   // SSSP: sources waiting for a later band at v
     uint32_t *dist = nullptr;             // SSSP: distances, vertex-major [V][64]
     uint32_t *hub[2] = {nullptr, nullptr};// queues of long lists (workgroup per vertex)
     unsigned long long *ctr = nullptr;    // queue lengths, level, flags
@@ -120,7 +121,7 @@ struct emogi_graph_s {
     emogi::Pool pool;
     emogi::BatchPool batch;
     emogi::Tier tier;
-    emogi_batch_params_t batch_params{1024, 4, 8, 1};
+    emogi_batch_params_t batch_params{1024, 4, 8, 1, 0};
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;
     emogi_stats_t stats{};

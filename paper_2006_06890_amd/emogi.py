@@ -113,6 +113,7 @@ class BatchParams(ctypes.Structure):
         ("steps_per_graph", ctypes.c_uint32),
         ("blocks_per_cu", ctypes.c_uint32),
         ("use_graph", ctypes.c_uint32),
+        ("sssp_delta", ctypes.c_uint32),
     ]
 
     def as_dict(self):
@@ -451,8 +452,9 @@ class Graph:
                                      _stream_handle(stream)))
         return out
 
-    def set_batch_params(self, hub_degree=1024, steps_per_graph=4, blocks_per_cu=8, use_graph=True):
-        p = BatchParams(hub_degree, steps_per_graph, blocks_per_cu, int(use_graph))
+    def set_batch_params(self, hub_degree=1024, steps_per_graph=4, blocks_per_cu=8, use_graph=True,
+                         sssp_delta=0):
+        p = BatchParams(hub_degree, steps_per_graph, blocks_per_cu, int(use_graph), sssp_delta)
         check(lib().emogi_set_batch_params(self._h, ctypes.byref(p)))
 
     def get_batch_params(self):

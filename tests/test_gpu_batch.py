@@ -78,6 +78,23 @@ def test_batch_matches_oracle(gpu_device, name, pi):
             _check(E, g, G, srcs, "sssp")
 
 
+@pytest.mark.parametrize("delta", [0, 1, 7, 1000, 0xFFFFFFFF])
+@pytest.mark.parametrize("name", ["rmat13", "path200", "directed"])
+def test_batch_sssp_bands(gpu_device, name, delta):
+    """Distance bands shared by the batch's sources (a source waits at a
+    vertex until its distance there falls below the split) give every
+    source Dijkstra's distances for any band width; one band (0) is the
+    unbanded batch."""
+    import paper_2006_06890_amd as E
+    g = graphs()[name]
+    with E.Graph(g.row_ptr, g.col, g.weights, symmetric=(name != "directed")) as G:
+        G.set_batch_params(sssp_delta=delta)
+        for n, seed in ((1, 3), (9, 4), (64, 5)):
+            _check(E, g, G, _sources(g, n, seed), "sssp")
+        G.set_batch_params(use_graph=False, sssp_delta=delta)
+        _check(E, g, G, _sources(g, 17, 6), "sssp")
+
+
 def test_batch_overflow(gpu_device):
     import paper_2006_06890_amd as E
     big = 0x80000000
