@@ -98,7 +98,8 @@ typedef struct {
     uint64_t request_bytes;      /* the same lists rounded out to the request unit R     */
     uint64_t tier_edges;         /* of edges_scanned, those read from the HBM tier       */
     uint64_t weights_read;       /* SSSP: weights read over the host link (a weight is
-                                    read only when its edge could improve the target) */
+                                    read only when its edge could improve the target:
+                                    dist(v) > dist(u) + the smallest weight into v)   */
     double total_ms;             /* whole traversal, HIP events on the caller's stream   */
     double expand_ms;            /* sum of the neighbour-scan kernels alone              */
     uint32_t expand_launches;    /* how many neighbour-scan kernels ran                  */
@@ -146,7 +147,9 @@ emogi_status_t emogi_host_free(void *p);
  * row_ptr     host uint64[num_vertices+1], row_ptr[0] == 0, non-decreasing;
  *             E = row_ptr[V].  Copied into GPU memory.
  * col         host array of E neighbour ids, col_bytes = 4 or 8, each < V.
- * weights     host uint32[E] edge weights (NULL: SSSP unavailable).
+ * weights     host uint32[E] edge weights (NULL: SSSP unavailable).  With
+ *             weights, creation reads the edge list once on the GPU to find
+ *             each vertex's smallest incoming weight (V bytes of GPU memory).
  * placement   where col and weights live (see emogi_placement_t).
  * Errors: EMOGI_E_INVALID (bad sizes, V >= 2^32-1, malformed CSR under
  * EMOGI_F_VALIDATE, BORROW of memory not from emogi_host_alloc),

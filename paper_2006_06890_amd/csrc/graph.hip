@@ -119,6 +119,7 @@ static void release(emogi_graph_s *g) {
     free_edges(g->col, g->col_kind);
     free_edges(g->weights, g->w_kind);
     if (g->row_ptr) (void)hipFree(g->row_ptr);
+    if (g->in_min) (void)hipFree(g->in_min);
     Pool &p = g->pool;
     for (auto q : p.queue)
         if (q) (void)hipFree(q);
@@ -152,6 +153,70 @@ static void release(emogi_graph_s *g) {
     for (hipEvent_t e : {g->ev_begin, g->ev_end, g->ev_k0, g->ev_k1})
         if (e) (void)hipEventDestroy(e);
     delete g;
+}
+
+// Smallest weight of an edge into each vertex: one coalesced pass over the
+// edge list (wherever it is placed) with atomicMin into m; ids at or above V
+// are ignored.  The plain read first skips atomics that cannot lower m[v].
+template <class ColT>
+__global__ __launch_bounds__(256) void k_in_min(const ColT *col, const uint32_t *w, uint64_t E, uint64_t V,
+                                                uint32_t *m) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < E; i += stride) {
+        const uint64_t v = uint64_t(col[i]);
+        const uint32_t x = w[i];
+        if (v < V && x < m[v]) atomicMin(&m[v], x);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_in_min_init(uint32_t *m, uint64_t V) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < V; i += stride) m[i] = 0xFFFFFFFFu;
+}
+
+__global__ __launch_bounds__(256) void k_in_min_pack(const uint32_t *m, uint64_t V, uint8_t *out) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < V; i += stride)
+        out[i] = uint8_t(min(m[i], 255u));
+}
+
+// Per-vertex smallest incoming weight (uint8, saturated) for SSSP's
+// weight-read skipping; computed from the edges, so it holds for directed
+// graphs and asymmetric weights alike.
+static emogi_status_t compute_in_min(emogi_graph_s *g) {
+    const uint64_t V = g->V, E = g->E;
+    uint32_t *m = nullptr;
+    if (hipMalloc(&m, V * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of %llu bytes for the incoming weight bounds failed",
+                  (unsigned long long)(V * sizeof(uint32_t)));
+        return EMOGI_E_OOM_DEVICE;
+    }
+    if (hipMalloc(&g->in_min, V) != hipSuccess) {
+        (void)hipGetLastError();
+        g->in_min = nullptr;
+        (void)hipFree(m);
+        set_error("hipMalloc of the incoming weight bounds failed");
+        return EMOGI_E_OOM_DEVICE;
+    }
+    const unsigned grid = 256u * 8u;
+    hipLaunchKernelGGL(k_in_min_init, dim3(grid), dim3(256), 0, nullptr, m, V);
+    if (g->col_bytes == 8)
+        hipLaunchKernelGGL(k_in_min<uint64_t>, dim3(grid), dim3(256), 0, nullptr,
+                           static_cast<const uint64_t *>(g->col), g->weights, E, V, m);
+    else
+        hipLaunchKernelGGL(k_in_min<uint32_t>, dim3(grid), dim3(256), 0, nullptr,
+                           static_cast<const uint32_t *>(g->col), g->weights, E, V, m);
+    hipLaunchKernelGGL(k_in_min_pack, dim3(grid), dim3(256), 0, nullptr, m, V, g->in_min);
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipDeviceSynchronize();
+    (void)hipFree(m);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("incoming weight bound kernels failed");
+        return EMOGI_E_HIP;
+    }
+    return EMOGI_OK;
 }
 
 // Places one edge-sized array (col or weights) per the placement.
@@ -349,6 +414,7 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
         void *w = nullptr;
         st = place(g, weights, E * sizeof(uint32_t), &w, &g->w_kind);
         g->weights = static_cast<uint32_t *>(w);
+        if (st == EMOGI_OK && E > 0) st = compute_in_min(g);
     }
     if (st == EMOGI_OK) {
         for (hipEvent_t *e : {&g->ev_begin, &g->ev_end, &g->ev_k0, &g->ev_k1})

@@ -117,6 +117,8 @@ struct emogi_graph_s {
     float *mlp_range = nullptr;    // device, 16 lower then 16 upper feature bounds, or null
     uint64_t max_degree = 0;
     uint32_t min_weight = 0;       // smallest edge weight (a bound for skipping weight reads)
+    uint8_t *in_min = nullptr;     // device, per vertex: smallest weight of an edge into it,
+                                   // saturated at 255 (a tighter bound of the same kind)
 
     emogi::Pool pool;
     emogi::BatchPool batch;

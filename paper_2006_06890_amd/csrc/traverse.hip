@@ -77,6 +77,7 @@ struct OpArgs {
     uint32_t *farbits;  // ... marked here
     uint32_t wmin;      // SSSP: no edge weight is smaller
     unsigned long long *ctr;
+    const uint8_t *inmin = nullptr;  // SSSP: per target, no weight of an edge into it is smaller
 };
 
 template <int A>
@@ -126,9 +127,11 @@ __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v,
         // SSSP: relax the edge; an improved vertex joins the next round when
         // its distance is inside the band, otherwise it waits, marked.  The
         // weight is read (over the host link) only when the edge can improve
-        // v: with dist(v) <= dist(u) + the smallest weight it cannot.
+        // v: with dist(v) <= dist(u) + the smallest weight of an edge into v
+        // it cannot.  Both bounds are HBM reads issued together.
         const uint32_t cur = a.state[v];
-        const uint64_t floor_nd = uint64_t(uval) + a.wmin;
+        const uint32_t lo = a.inmin ? max(a.wmin, uint32_t(a.inmin[v])) : a.wmin;
+        const uint64_t floor_nd = uint64_t(uval) + lo;
         if (floor_nd <= 0xFFFFFFFEull && cur <= floor_nd) return 0;
         const uint64_t nd = uint64_t(uval) + *wp;
         if (nd > 0xFFFFFFFEull) {
@@ -1366,6 +1369,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             a.split = split;
             a.farbits = p.farbits;
             a.wmin = g->min_weight;
+            a.inmin = g->in_min;
             EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
                           EMOGI_E_HIP);
             if (v == EMOGI_V5_BALANCED) {

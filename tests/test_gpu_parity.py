@@ -238,11 +238,46 @@ def test_sssp_weight_skipping_bounds(gpu_device, wkind):
                                                   err_msg=f"{name} {wkind} V{v} s{s}")
                     st = G.stats()
                     assert st["weights_read"] <= st["edges_scanned"]
+                    # every reached vertex but the source took one weight at least
+                    reached = int((E.to_u32(out) != 0xFFFFFFFF).sum())
+                    assert st["weights_read"] >= reached - 1
                     assert st["useful_link_bytes"] == st["edges_scanned"] * 4 + st["weights_read"] * 4
         if name == "star5000":
             with E.Graph(g.row_ptr, g.col, w) as G:
                 G.sssp(0, out)
                 assert G.stats()["weights_read"] == g.num_edges // 2  # every leaf improves once
+
+
+def test_sssp_incoming_weight_bound(gpu_device):
+    """The weight-read bound is the smallest weight of an edge INTO the
+    target.  Vertex 1 is reached at 10 first (0->1), then improved to 2 via
+    0->2->1; its own out-edge weighs 200, so a bound taken from the wrong end
+    (or the largest instead of the smallest weight) would skip 2->1.  Chains
+    of heavy edges (weights above 255) check the saturated bound."""
+    import torch
+    E = _emogi()
+    edges = [(0, 1, 10), (0, 2, 1), (2, 1, 1), (1, 3, 200), (3, 4, 300), (4, 5, 1000),
+             (0, 5, 5000), (2, 6, 256), (6, 5, 256), (5, 7, 7)]
+    V = 8
+    edges.sort()
+    rp = np.zeros(V + 1, dtype=np.uint64)
+    for u, _, _ in edges:
+        rp[u + 1] += 1
+    rp = np.cumsum(rp).astype(np.uint64)
+    col = np.array([v for _, v, _ in edges], dtype=np.uint32)
+    w = np.array([x for _, _, x in edges], dtype=np.uint32)
+    out = torch.empty(V, dtype=torch.int32, device="cuda")
+    exp = oracle.dijkstra(rp, col, w, 0)
+    assert list(exp[:8]) == [0, 2, 1, 202, 502, 513, 257, 520]
+    with E.Graph(rp, col, w) as G:
+        for delta in (0, 1, 3, 1000):
+            G.set_sssp_delta(delta)
+            for v in range(6):
+                G.set_variant(v)
+                G.sssp(0, out)
+                np.testing.assert_array_equal(E.to_u32(out), exp, err_msg=f"delta {delta} V{v}")
+                st = G.stats()
+                assert 7 <= st["weights_read"] <= st["edges_scanned"]
 
 
 def test_directed_sssp_delta(gpu_device):
