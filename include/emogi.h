@@ -99,7 +99,8 @@ typedef struct {
     uint64_t tier_edges;         /* of edges_scanned, those read from the HBM tier       */
     uint64_t weights_read;       /* SSSP: weights read over the host link (a weight is
                                     read only when its edge could improve the target:
-                                    dist(v) > dist(u) + the smallest weight into v)   */
+                                    dist(v) > dist(u) + the smallest weight into v,
+                                    or into any vertex when the edges are in HBM)     */
     double total_ms;             /* whole traversal, HIP events on the caller's stream   */
     double expand_ms;            /* sum of the neighbour-scan kernels alone              */
     uint32_t expand_launches;    /* how many neighbour-scan kernels ran                  */
@@ -148,8 +149,9 @@ emogi_status_t emogi_host_free(void *p);
  *             E = row_ptr[V].  Copied into GPU memory.
  * col         host array of E neighbour ids, col_bytes = 4 or 8, each < V.
  * weights     host uint32[E] edge weights (NULL: SSSP unavailable).  With
- *             weights, creation reads the edge list once on the GPU to find
- *             each vertex's smallest incoming weight (V bytes of GPU memory).
+ *             weights in host zero-copy placement, creation reads the edge
+ *             list once on the GPU to find each vertex's smallest incoming
+ *             weight (V bytes of GPU memory).
  * placement   where col and weights live (see emogi_placement_t).
  * Errors: EMOGI_E_INVALID (bad sizes, V >= 2^32-1, malformed CSR under
  * EMOGI_F_VALIDATE, BORROW of memory not from emogi_host_alloc),

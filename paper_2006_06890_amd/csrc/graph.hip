@@ -414,7 +414,9 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
         void *w = nullptr;
         st = place(g, weights, E * sizeof(uint32_t), &w, &g->w_kind);
         g->weights = static_cast<uint32_t *>(w);
-        if (st == EMOGI_OK && E > 0) st = compute_in_min(g);
+        // the per-target bound pays only where a weight read crosses the
+        // host link; from HBM the extra gather costs more than it saves
+        if (st == EMOGI_OK && E > 0 && placement == EMOGI_PLACE_HOST_ZERO_COPY) st = compute_in_min(g);
     }
     if (st == EMOGI_OK) {
         for (hipEvent_t *e : {&g->ev_begin, &g->ev_end, &g->ev_k0, &g->ev_k1})

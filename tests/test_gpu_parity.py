@@ -269,15 +269,16 @@ def test_sssp_incoming_weight_bound(gpu_device):
     out = torch.empty(V, dtype=torch.int32, device="cuda")
     exp = oracle.dijkstra(rp, col, w, 0)
     assert list(exp[:8]) == [0, 2, 1, 202, 502, 513, 257, 520]
-    with E.Graph(rp, col, w) as G:
-        for delta in (0, 1, 3, 1000):
-            G.set_sssp_delta(delta)
-            for v in range(6):
-                G.set_variant(v)
-                G.sssp(0, out)
-                np.testing.assert_array_equal(E.to_u32(out), exp, err_msg=f"delta {delta} V{v}")
-                st = G.stats()
-                assert 7 <= st["weights_read"] <= st["edges_scanned"]
+    for placement in ("host_zero_copy", "hbm"):
+        with E.Graph(rp, col, w, placement=placement) as G:
+            for delta in (0, 1, 3, 1000):
+                G.set_sssp_delta(delta)
+                for v in range(6):
+                    G.set_variant(v)
+                    G.sssp(0, out)
+                    np.testing.assert_array_equal(E.to_u32(out), exp, err_msg=f"{placement} delta {delta} V{v}")
+                    st = G.stats()
+                    assert 7 <= st["weights_read"] <= st["edges_scanned"]
 
 
 def test_directed_sssp_delta(gpu_device):
