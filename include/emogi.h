@@ -63,6 +63,7 @@ typedef enum {
                                         in place (zero-copy placement only); the caller keeps them
                                         alive and unmodified until emogi_graph_destroy */
 #define EMOGI_F_PIN_NONCOHERENT 0x8u /* pinned edge list allocated non-coherent */
+#define EMOGI_F_PACK 0x10u           /* store the lists compressed (see emogi_packed_bytes) */
 
 /* Access variants of the neighbour scan (all give identical results). */
 typedef enum {
@@ -94,7 +95,9 @@ typedef struct {
     uint64_t vertices_expanded;  /* frontier entries whose lists were scanned            */
     uint64_t edges_scanned;      /* sum of their out-degrees (re-expansions included)    */
     uint64_t useful_link_bytes;  /* (edges_scanned - tier_edges) * col_bytes
-                                    + 4 * weights_read: bytes the lists need from the link */
+                                    + 4 * weights_read: bytes the lists need from the link
+                                    (packed graphs: the encoded bytes of the lists scanned
+                                    + 4 * weights_read)                                     */
     uint64_t request_bytes;      /* the same lists rounded out to the request unit R     */
     uint64_t tier_edges;         /* of edges_scanned, those read from the HBM tier       */
     uint64_t weights_read;       /* SSSP: weights read over the host link (a weight is
@@ -157,12 +160,23 @@ emogi_status_t emogi_host_free(void *p);
  * EMOGI_F_VALIDATE, BORROW of memory not from emogi_host_alloc),
  * EMOGI_E_NOT_SYMMETRIC (EMOGI_F_VALIDATE|EMOGI_F_SYMMETRIC on an asymmetric
  * graph), EMOGI_E_OOM_*, EMOGI_E_UNSUPPORTED (placement not available).
+ * EMOGI_F_PACK stores the lists compressed, the data compression with
+ * decoding on the GPU that Sec. 6 proposes to cut link traffic: each list
+ * (ascending ids required, else EMOGI_E_INVALID) is cut into blocks of 64
+ * ids, a block being its first id as a 32-bit word and then the gaps to the
+ * next ids bit-packed at the list's gap width.  The blocks go where the
+ * placement puts the lists; col is read only during creation; weights stay
+ * as given.  BFS, SSSP, CC and PageRank scan packed lists with the
+ * edge-balanced variant (V5) whatever the scheduler; batched traversal and
+ * the HBM tier are EMOGI_E_UNSUPPORTED on packed graphs.
  * Nothing is leaked on failure; *out is set only on success. */
 emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t num_vertices,
                                   const void *col, uint32_t col_bytes,
                                   const uint32_t *weights, emogi_placement_t placement,
                                   uint32_t flags, emogi_graph_t *out);
 emogi_status_t emogi_graph_destroy(emogi_graph_t g);
+/* Bytes of the packed lists (0 for a graph created without EMOGI_F_PACK). */
+emogi_status_t emogi_packed_bytes(emogi_graph_t g, uint64_t *bytes);
 
 /* Request unit R (bytes, power of two 32..4096) used to round list starts
  * down (Sec. 4.3.2).  Default 256: the smallest block that runs the MI355X

@@ -537,6 +537,10 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
         set_error("batched traversal needs 1..64 sources and an output");
         return EMOGI_E_INVALID;
     }
+    if (g->packed.stream) {
+        set_error("batched traversal reads plain lists; this graph's lists are packed");
+        return EMOGI_E_UNSUPPORTED;
+    }
     for (uint32_t i = 0; i < n; ++i)
         if (srcs[i] >= g->V) {
             set_error("source %llu out of range", (unsigned long long)srcs[i]);
@@ -752,6 +756,10 @@ emogi_status_t emogi_autotune_batch(emogi_graph_t g, int algo, const uint64_t *s
     if (!g || (algo != 0 && algo != 1)) {
         set_error("autotune: algo must be 0 (BFS) or 1 (SSSP)");
         return EMOGI_E_INVALID;
+    }
+    if (g->packed.stream) {
+        set_error("batched traversal reads plain lists; this graph's lists are packed");
+        return EMOGI_E_UNSUPPORTED;
     }
     // Candidate grid: hub threshold x level steps per replay x occupancy.
     const uint32_t hubs[] = {256, 1024, 8192};

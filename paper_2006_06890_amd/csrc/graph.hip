@@ -120,6 +120,10 @@ static void release(emogi_graph_s *g) {
     free_edges(g->weights, g->w_kind);
     if (g->row_ptr) (void)hipFree(g->row_ptr);
     if (g->in_min) (void)hipFree(g->in_min);
+    if (g->packed.on_device && g->packed.stream) (void)hipFree(g->packed.stream);
+    if (g->packed.pinned) (void)hipHostFree(g->packed.pinned);
+    if (g->packed.off) (void)hipFree(g->packed.off);
+    if (g->packed.width) (void)hipFree(g->packed.width);
     Pool &p = g->pool;
     for (auto q : p.queue)
         if (q) (void)hipFree(q);
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(256) void k_in_min_pack(const uint32_t *m, uint64_t
 // Per-vertex smallest incoming weight (uint8, saturated) for SSSP's
 // weight-read skipping; computed from the edges, so it holds for directed
 // graphs and asymmetric weights alike.
-static emogi_status_t compute_in_min(emogi_graph_s *g) {
+static emogi_status_t compute_in_min(emogi_graph_s *g, const void *col_host) {
     const uint64_t V = g->V, E = g->E;
     uint32_t *m = nullptr;
     if (hipMalloc(&m, V * sizeof(uint32_t)) != hipSuccess) {
@@ -201,14 +205,35 @@ static emogi_status_t compute_in_min(emogi_graph_s *g) {
     }
     const unsigned grid = 256u * 8u;
     hipLaunchKernelGGL(k_in_min_init, dim3(grid), dim3(256), 0, nullptr, m, V);
-    if (g->col_bytes == 8)
-        hipLaunchKernelGGL(k_in_min<uint64_t>, dim3(grid), dim3(256), 0, nullptr,
-                           static_cast<const uint64_t *>(g->col), g->weights, E, V, m);
-    else
-        hipLaunchKernelGGL(k_in_min<uint32_t>, dim3(grid), dim3(256), 0, nullptr,
-                           static_cast<const uint32_t *>(g->col), g->weights, E, V, m);
+    auto run = [&](const void *c, const uint32_t *w, uint64_t n) {
+        if (g->col_bytes == 8)
+            hipLaunchKernelGGL(k_in_min<uint64_t>, dim3(grid), dim3(256), 0, nullptr,
+                               static_cast<const uint64_t *>(c), w, n, V, m);
+        else
+            hipLaunchKernelGGL(k_in_min<uint32_t>, dim3(grid), dim3(256), 0, nullptr,
+                               static_cast<const uint32_t *>(c), w, n, V, m);
+    };
+    hipError_t e0 = hipSuccess;
+    if (g->col) {
+        run(g->col, g->weights, E);
+    } else {
+        // a packed graph keeps no id array the GPU can read: stage slices of
+        // the caller's ids in GPU memory (null-stream order keeps the slice
+        // buffer from being overwritten while a kernel still reads it)
+        const uint64_t slice = uint64_t(1) << 26;
+        void *stage = nullptr;
+        e0 = hipMalloc(&stage, std::min(slice, E) * g->col_bytes);
+        for (uint64_t i0 = 0; e0 == hipSuccess && i0 < E; i0 += slice) {
+            const uint64_t n = std::min(slice, E - i0);
+            e0 = hipMemcpy(stage, static_cast<const char *>(col_host) + i0 * g->col_bytes, n * g->col_bytes,
+                           hipMemcpyHostToDevice);
+            if (e0 == hipSuccess) run(stage, g->weights + i0, n);
+        }
+        (void)hipDeviceSynchronize();
+        if (stage) (void)hipFree(stage);
+    }
     hipLaunchKernelGGL(k_in_min_pack, dim3(grid), dim3(256), 0, nullptr, m, V, g->in_min);
-    const hipError_t e1 = hipGetLastError();
+    const hipError_t e1 = e0 != hipSuccess ? e0 : hipGetLastError();
     const hipError_t e2 = hipDeviceSynchronize();
     (void)hipFree(m);
     if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -216,6 +241,120 @@ static emogi_status_t compute_in_min(emogi_graph_s *g) {
         set_error("incoming weight bound kernels failed");
         return EMOGI_E_HIP;
     }
+    return EMOGI_OK;
+}
+
+// EMOGI_F_PACK: encodes the lists on the host threads in two passes over col
+// (gap widths and word counts, then the blocks) straight into the stream's
+// final host memory (pinned) or a host buffer copied to HBM.
+static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, const void *col) {
+    const uint64_t V = g->V;
+    const uint32_t cb = g->col_bytes;
+    if (g->placement == EMOGI_PLACE_MANAGED) {
+        set_error("packed lists are placed in pinned host memory or HBM, not managed memory");
+        return EMOGI_E_UNSUPPORTED;
+    }
+    std::vector<uint8_t> width(V);
+    std::vector<uint64_t> off(V + 1, 0);
+    std::atomic<uint64_t> bad{~uint64_t(0)};
+    parallel_for(V, [&](uint64_t u0, uint64_t u1) {
+        for (uint64_t u = u0; u < u1; ++u) {
+            const uint64_t b = row_ptr[u], e = row_ptr[u + 1];
+            uint64_t maxgap = 0, prev = 0;
+            for (uint64_t i = b; i < e; ++i) {
+                const uint64_t x = col_at(col, cb, i);
+                if (x > 0xFFFFFFFFull || (i > b && x < prev)) {
+                    uint64_t cur = bad.load();
+                    while (u < cur && !bad.compare_exchange_weak(cur, u)) {
+                    }
+                }
+                if ((i - b) % 64 != 0 && x >= prev) maxgap = std::max(maxgap, x - prev);
+                prev = x;
+            }
+            const uint32_t w = maxgap ? 64u - uint32_t(__builtin_clzll(maxgap)) : 0u;
+            width[u] = uint8_t(w);
+            const uint64_t d = e - b;
+            if (d) {
+                const uint64_t nb = (d + 63) / 64, last = d - (nb - 1) * 64;
+                off[u + 1] = (nb - 1) * (1 + (63 * uint64_t(w) + 31) / 32) + 1 + ((last - 1) * w + 31) / 32;
+            }
+        }
+    });
+    if (bad.load() != ~uint64_t(0)) {
+        set_error("EMOGI_F_PACK needs ascending lists of ids below 2^32 (vertex %llu)",
+                  (unsigned long long)bad.load());
+        return EMOGI_E_INVALID;
+    }
+    for (uint64_t u = 0; u < V; ++u) off[u + 1] += off[u];
+    const uint64_t words = off[V];
+    const size_t bytes = std::max<size_t>(8, words * 4);
+    uint32_t *host = nullptr;
+    std::vector<uint32_t> staging;
+    Packed &pk = g->packed;
+    if (g->placement == EMOGI_PLACE_HOST_ZERO_COPY) {
+        unsigned fl = hipHostMallocMapped;
+        if (g->flags & EMOGI_F_PIN_NONCOHERENT) fl |= hipHostMallocNonCoherent;
+        void *h = nullptr;
+        if (hipHostMalloc(&h, bytes, fl) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipHostMalloc of %zu pinned bytes for the packed lists failed", bytes);
+            return EMOGI_E_OOM_HOST;
+        }
+        pk.pinned = h;
+        host = static_cast<uint32_t *>(h);
+    } else {
+        staging.resize(bytes / 4);
+        host = staging.data();
+    }
+    parallel_for(V, [&](uint64_t u0, uint64_t u1) {
+        for (uint64_t u = u0; u < u1; ++u) {
+            const uint64_t b = row_ptr[u], e = row_ptr[u + 1];
+            const uint32_t w = width[u];
+            uint32_t *o = host + off[u];
+            for (uint64_t k0 = b; k0 < e; k0 += 64) {
+                const uint64_t k1 = std::min(e, k0 + 64);
+                uint64_t prev = col_at(col, cb, k0), acc = 0;
+                uint32_t nbits = 0;
+                *o++ = uint32_t(prev);
+                for (uint64_t i = k0 + 1; i < k1; ++i) {
+                    const uint64_t x = col_at(col, cb, i);
+                    acc |= (x - prev) << nbits;  // nbits < 32 and gap < 2^w, w <= 32
+                    nbits += w;
+                    prev = x;
+                    if (nbits >= 32) {
+                        *o++ = uint32_t(acc);
+                        acc >>= 32;
+                        nbits -= 32;
+                    }
+                }
+                if (nbits) *o++ = uint32_t(acc);
+            }
+        }
+    });
+    pk.words = words;
+    if (g->placement == EMOGI_PLACE_HOST_ZERO_COPY) {
+        void *d = nullptr;
+        EMOGI_HIP_TRY(hipHostGetDevicePointer(&d, pk.pinned, 0), EMOGI_E_HIP);
+        pk.stream = static_cast<uint32_t *>(d);
+    } else {
+        void *d = nullptr;
+        if (hipMalloc(&d, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of %zu bytes for the packed lists failed", bytes);
+            return EMOGI_E_OOM_DEVICE;
+        }
+        pk.stream = static_cast<uint32_t *>(d);
+        pk.on_device = true;
+        EMOGI_HIP_TRY(hipMemcpy(d, host, bytes, hipMemcpyHostToDevice), EMOGI_E_HIP);
+    }
+    if (hipMalloc(&pk.off, (V + 1) * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc(&pk.width, std::max<uint64_t>(V, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of the packed list offsets failed");
+        return EMOGI_E_OOM_DEVICE;
+    }
+    EMOGI_HIP_TRY(hipMemcpy(pk.off, off.data(), (V + 1) * sizeof(uint64_t), hipMemcpyHostToDevice), EMOGI_E_HIP);
+    if (V) EMOGI_HIP_TRY(hipMemcpy(pk.width, width.data(), V, hipMemcpyHostToDevice), EMOGI_E_HIP);
     return EMOGI_OK;
 }
 
@@ -409,14 +548,17 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
         set_error("copy of row_ptr failed");
         return EMOGI_E_HIP;
     }
-    st = place(g, col, E * col_bytes, &g->col, &g->col_kind);
+    if (flags & EMOGI_F_PACK)
+        st = pack_lists(g, row_ptr, col);  // g->col stays null: the scans decode the packed lists
+    else
+        st = place(g, col, E * col_bytes, &g->col, &g->col_kind);
     if (st == EMOGI_OK && weights) {
         void *w = nullptr;
         st = place(g, weights, E * sizeof(uint32_t), &w, &g->w_kind);
         g->weights = static_cast<uint32_t *>(w);
         // the per-target bound pays only where a weight read crosses the
         // host link; from HBM the extra gather costs more than it saves
-        if (st == EMOGI_OK && E > 0 && placement == EMOGI_PLACE_HOST_ZERO_COPY) st = compute_in_min(g);
+        if (st == EMOGI_OK && E > 0 && placement == EMOGI_PLACE_HOST_ZERO_COPY) st = compute_in_min(g, col);
     }
     if (st == EMOGI_OK) {
         for (hipEvent_t *e : {&g->ev_begin, &g->ev_end, &g->ev_k0, &g->ev_k1})
@@ -432,6 +574,15 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
         return st;
     }
     *out = g;
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_packed_bytes(emogi_graph_t g, uint64_t *bytes) {
+    if (!g || !bytes) {
+        set_error("null argument");
+        return EMOGI_E_INVALID;
+    }
+    *bytes = g->packed.words * 4;
     return EMOGI_OK;
 }
 

@@ -36,7 +36,8 @@ enum Counter : int {
     C_FEAT = 7,      // scheduler: the next frontier's 16 features (fp32, 8 slots)
     C_TIER = 15,     // edges of expanded vertices whose lists were read from the HBM tier
     C_WLINK = 16,    // SSSP: weights read over the host link
-    C_COUNT = 17
+    C_PKBYTES = 17,  // packed lists: encoded bytes of the lists scanned
+    C_COUNT = 18
 };
 
 // HBM tier of neighbour lists (device arrays; see tier.h).
@@ -49,6 +50,20 @@ struct Tier {
     uint32_t n = 0;
     uint64_t elems = 0;         // list elements held
     uint64_t bytes = 0;         // device bytes of col + w
+};
+
+// Packed neighbour lists (EMOGI_F_PACK).  Each list is cut into blocks of
+// 64 ids; a block is its first id as a whole word, then the gaps to the next
+// ids (at most 63) at the list's gap width, bit-packed into words.  Every
+// block but a list's last is full, so block k of list u starts at word
+// off[u] + k * (1 + ceil(63 * width[u] / 32)).
+struct Packed {
+    uint32_t *stream = nullptr;  // the blocks of all lists, as the GPU addresses them
+    void *pinned = nullptr;      // host allocation behind stream (zero-copy placement)
+    bool on_device = false;      // stream is in HBM
+    uint64_t *off = nullptr;     // HBM, V + 1 word offsets
+    uint8_t *width = nullptr;    // HBM, V gap widths in bits (0..32)
+    uint64_t words = 0;          // stream length
 };
 
 struct Pool {
@@ -123,6 +138,7 @@ struct emogi_graph_s {
     emogi::Pool pool;
     emogi::BatchPool batch;
     emogi::Tier tier;
+    emogi::Packed packed;           // set for EMOGI_F_PACK graphs (col is then null)
     emogi_batch_params_t batch_params{1024, 4, 8, 1, 0};
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;

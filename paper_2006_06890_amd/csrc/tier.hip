@@ -91,6 +91,10 @@ emogi_status_t emogi_set_hbm_tier(emogi_graph_t g, uint64_t budget_bytes, uint64
         set_error("null graph");
         return EMOGI_E_INVALID;
     }
+    if (g->packed.stream) {
+        set_error("the HBM tier copies plain lists; this graph's lists are packed");
+        return EMOGI_E_UNSUPPORTED;
+    }
     EMOGI_HIP_TRY(hipDeviceSynchronize(), EMOGI_E_HIP);
     tier_release(g);
     if (tier_vertices) *tier_vertices = 0;

@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -40,19 +41,22 @@ constexpr int kMaxGrid = 256 * 8; // 8 blocks of 4 waves on each of the 256 CUs
 // End of a scan block: flush the staged frontier and fold the statistics.
 __device__ __forceinline__ void finish_block(Stage &st, uint32_t *next, unsigned long long *ctr,
                                              int lane, int wid, uint64_t edges, uint64_t reqb,
-                                             uint64_t verts, uint64_t tedges, uint64_t wlink = 0) {
+                                             uint64_t verts, uint64_t tedges, uint64_t wlink = 0,
+                                             uint64_t pkb = 0) {
     finish_queue(st, next, &ctr[C_NEXT], lane, wid);
     edges = wave_sum64(edges);
     reqb = wave_sum64(reqb);
     verts = wave_sum64(verts);
     tedges = wave_sum64(tedges);
     wlink = wave_sum64(wlink);
+    pkb = wave_sum64(pkb);
     if (lane == 0) {
         if (edges) atomicAdd(&ctr[C_EDGES], (unsigned long long)edges);
         if (reqb) atomicAdd(&ctr[C_REQBYTES], (unsigned long long)reqb);
         if (verts) atomicAdd(&ctr[C_VERTS], (unsigned long long)verts);
         if (tedges) atomicAdd(&ctr[C_TIER], (unsigned long long)tedges);
         if (wlink) atomicAdd(&ctr[C_WLINK], (unsigned long long)wlink);
+        if (pkb) atomicAdd(&ctr[C_PKBYTES], (unsigned long long)pkb);
     }
 }
 
@@ -184,7 +188,29 @@ struct ScanArgs {
     uint32_t col_bytes;
     const uint64_t *chunk_scan;  // V5 only
     TierView tier;               // HBM copies of hub lists (tier.bits null: none)
+    const uint32_t *pk = nullptr;        // packed lists (EMOGI_F_PACK; col is then unused)
+    const uint64_t *pk_off = nullptr;    // word offset of each packed list (V + 1)
+    const uint8_t *pk_width = nullptr;   // gap width of each packed list, bits
 };
+
+// Tag for packed lists in the ColT slot of the V5 and PageRank kernels.
+struct PackedCol {
+    uint32_t x;
+};
+template <class ColT>
+constexpr bool kPacked = std::is_same<ColT, PackedCol>::value;
+
+// Words of a full packed block (first id + 63 gaps of w bits).
+__device__ __forceinline__ uint32_t packed_block_words(uint32_t w) { return 1u + (63u * w + 31u) / 32u; }
+
+// Inclusive prefix sum over the 64 lanes (every lane calls it).
+__device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t x, int lane) {
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
 
 __device__ __forceinline__ uint64_t request_bytes(uint64_t s, uint64_t e, uint32_t cb, uint32_t R) {
     uint64_t first = (s * cb) / R, last = (e * cb + R - 1) / R;
@@ -198,6 +224,16 @@ __device__ __forceinline__ void count_list(bool tier, uint64_t b, uint64_t e, ui
     verts += 1;
     if (tier) tedges += e - b;
     else reqb += request_bytes(b, e, cb, R);
+}
+
+// A packed list counts its edges, its encoded words [w0, w1) as bytes, and
+// those rounded out to the request unit.
+__device__ __forceinline__ void count_packed(uint64_t b, uint64_t e, uint64_t w0, uint64_t w1, uint32_t R,
+                                             uint64_t &edges, uint64_t &reqb, uint64_t &verts, uint64_t &pkb) {
+    edges += e - b;
+    verts += 1;
+    reqb += request_bytes(w0, w1, 4, R);
+    pkb += (w1 - w0) * 4;
 }
 
 __device__ __forceinline__ uint32_t frontier_at(const ScanArgs &s, uint32_t q) {
@@ -379,6 +415,8 @@ struct ChunkCursor {
     uint32_t u, uval;
     uint64_t b, e;
     ListSrc<ColT> src;
+    uint64_t pw0, pw1;       // packed: the list's words [pw0, pw1)
+    uint32_t pwidth, pfull;  // packed: gap width, words per full block
 };
 
 // kUnroll chunks' neighbours (and weights), loaded, not yet visited.
@@ -390,6 +428,9 @@ struct ChunkGroup {
     uint32_t uv[kUnroll];
     uint64_t wbase[kUnroll];
     bool tier[kUnroll];
+    // packed lists: the word after v[i] (when the gap straddles it), the bit
+    // shift and the gap width, decoded once the loads are back
+    uint32_t hi[kUnroll], sh[kUnroll], pw[kUnroll];
 };
 
 template <class ColT, int A>
@@ -399,6 +440,12 @@ __device__ __forceinline__ void enter_entry(ChunkCursor<ColT> &c, const ScanArgs
     c.e = uniform64(s.row_ptr[c.u + 1]);
     c.uval = uniform32(source_value<A>(a, c.u));
     c.src = list_src(s.tier, static_cast<const ColT *>(s.col), s.w, c.u, c.b);
+    if constexpr (kPacked<ColT>) {
+        c.pw0 = uniform64(s.pk_off[c.u]);
+        c.pw1 = uniform64(s.pk_off[c.u + 1]);
+        c.pwidth = uniform32(s.pk_width[c.u]);
+        c.pfull = packed_block_words(c.pwidth);
+    }
 }
 
 template <class ColT, int A>
@@ -420,7 +467,7 @@ __device__ __forceinline__ void open_run(ChunkCursor<ColT> &c, const ScanArgs &s
 template <class ColT, int A>
 __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, const ScanArgs &s, const OpArgs &a,
                                            int lane, uint64_t &edges, uint64_t &reqb, uint64_t &verts,
-                                           uint64_t &tedges) {
+                                           uint64_t &tedges, uint64_t &pkb) {
 #pragma unroll
     for (int i = 0; i < kUnroll; ++i) {
         const uint64_t kk = c.kb + i;
@@ -429,6 +476,9 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
         g.wbase[i] = 0;
         g.tier[i] = false;
         g.uv[i] = c.uval;
+        g.hi[i] = 0;
+        g.sh[i] = 0;
+        g.pw[i] = 0;
         if (kk < c.kend) {
             while (kk >= c.qnext) {  // next entry that owns chunks (uniform)
                 ++c.q;
@@ -437,14 +487,49 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
                 if (c.qnext > c.qfirst) enter_entry<ColT, A>(c, s, a);
             }
             g.uv[i] = c.uval;
-            if (kk == c.qfirst && lane == 0)
-                count_list(c.src.tier, c.b, c.e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
+            if (kk == c.qfirst && lane == 0) {
+                if constexpr (kPacked<ColT>)
+                    count_packed(c.b, c.e, c.pw0, c.pw1, s.req_unit, edges, reqb, verts, pkb);
+                else
+                    count_list(c.src.tier, c.b, c.e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
+            }
             const uint64_t j0 = uniform64((c.b & ~s.align_mask) + (kk - c.qfirst) * kWave);
             const uint64_t j = j0 + lane;
             g.ok[i] = (j >= c.b) && (j < c.e);
             if (A == A_SSSP) g.wbase[i] = uniform64(reinterpret_cast<uint64_t>(c.src.w + (j0 - c.src.shift)));
             g.tier[i] = c.src.tier;
-            if (g.ok[i]) g.v[i] = load_col(c.src.col, j - c.src.shift);
+            if constexpr (kPacked<ColT>) {
+                // block kk - qfirst of the list (chunks of a packed list are its
+                // blocks: align_mask is 0): lane 0 reads the block's first id,
+                // lane l the gap to id l, bits [(l-1)w, lw) after that word
+                const uint64_t wb = c.pw0 + (kk - c.qfirst) * c.pfull;
+                const uint32_t w = c.pwidth;
+                g.pw[i] = w;
+                if (g.ok[i]) {
+                    if (lane == 0) {
+                        g.v[i] = s.pk[wb];
+                    } else if (w) {
+                        const uint64_t o = uint64_t(lane - 1) * w;
+                        const uint64_t wd = wb + 1 + (o >> 5);
+                        g.sh[i] = uint32_t(o & 31u);
+                        g.v[i] = s.pk[wd];
+                        if (g.sh[i] + w > 32u) g.hi[i] = s.pk[wd + 1];
+                    }
+                }
+            } else {
+                if (g.ok[i]) g.v[i] = load_col(c.src.col, j - c.src.shift);
+            }
+        }
+    }
+    if constexpr (kPacked<ColT>) {
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) {
+            uint32_t x = g.v[i];
+            if (lane != 0) {
+                const uint64_t word = (uint64_t(g.hi[i]) << 32) | g.v[i];
+                x = uint32_t((word >> g.sh[i]) & ((uint64_t(1) << g.pw[i]) - 1));
+            }
+            g.v[i] = wave_prefix_sum(x, lane);  // first id + the gaps up to each lane
         }
     }
     c.kb += kUnroll;
@@ -461,14 +546,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0;
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0, pkb = 0;
     ChunkCursor<ColT> c;
     c.total = s.chunk_scan[s.n];
     c.stride = uint64_t(gridDim.x) * kWavesPerBlock * kChunksPerWave;
     open_run<ColT, A>(c, s, a, (uint64_t(blockIdx.x) * kWavesPerBlock + wid) * kChunksPerWave);
     while (c.kb < c.kend) {
         ChunkGroup g;
-        load_group<ColT, A>(c, g, s, a, lane, edges, reqb, verts, tedges);
+        load_group<ColT, A>(c, g, s, a, lane, edges, reqb, verts, tedges, pkb);
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i) {
             const int r = g.ok[i] ? visit<A>(a, g.uv[i], g.v[i], reinterpret_cast<const uint32_t *>(g.wbase[i]) + lane) : 0;
@@ -476,7 +561,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
             emit<A>(st, r & 3, g.v[i], s.next, a, lane);
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink);
+    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink, pkb);
 }
 
 // ---------------------------------------------------------------------------
@@ -497,14 +582,14 @@ template <class ColT>
 __global__ __launch_bounds__(kBlock) void k_pr_pull(ScanArgs s, PrArgs pa) {
     const int lane = lane_id();
     OpArgs a{};  // the cursor reads only source_value<A_LINK>, which is the vertex id
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0;
+    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, pkb = 0;
     ChunkCursor<ColT> c;
     c.total = s.chunk_scan[s.n];
     c.stride = uint64_t(gridDim.x) * kWavesPerBlock * kChunksPerWave;
     open_run<ColT, A_LINK>(c, s, a, (uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * kChunksPerWave);
     while (c.kb < c.kend) {
         ChunkGroup g;
-        load_group<ColT, A_LINK>(c, g, s, a, lane, edges, reqb, verts, tedges);
+        load_group<ColT, A_LINK>(c, g, s, a, lane, edges, reqb, verts, tedges, pkb);
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i) {
             const uint64_t x = (g.ok[i] && g.v[i] < s.n) ? pa.contrib[g.v[i]] : 0ull;
@@ -516,11 +601,13 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull(ScanArgs s, PrArgs pa) {
     reqb = wave_sum64(reqb);
     verts = wave_sum64(verts);
     tedges = wave_sum64(tedges);
+    pkb = wave_sum64(pkb);
     if (lane == 0) {
         if (edges) atomicAdd(&pa.ctr[C_EDGES], (unsigned long long)edges);
         if (reqb) atomicAdd(&pa.ctr[C_REQBYTES], (unsigned long long)reqb);
         if (verts) atomicAdd(&pa.ctr[C_VERTS], (unsigned long long)verts);
         if (tedges) atomicAdd(&pa.ctr[C_TIER], (unsigned long long)tedges);
+        if (pkb) atomicAdd(&pa.ctr[C_PKBYTES], (unsigned long long)pkb);
     }
 }
 
@@ -779,6 +866,36 @@ __global__ __launch_bounds__(kBlock) void k_cc_sample(const uint64_t *row_ptr, c
     if (lane_id() == 0 && tedges) atomicAdd(&ctr[C_TIER], (unsigned long long)tedges);
 }
 
+// Sampled hooking on packed lists: the first ids of block 0 of each list.
+__global__ __launch_bounds__(kBlock) void k_cc_sample_packed(const uint64_t *row_ptr, const uint32_t *pk,
+                                                             const uint64_t *pk_off, const uint8_t *pk_width,
+                                                             uint64_t V, uint32_t *parent,
+                                                             unsigned long long *ctr) {
+    uint64_t edges = 0;
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
+         v += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t d = row_ptr[v + 1] - row_ptr[v];
+        const uint32_t n = d < kCcSample ? uint32_t(d) : uint32_t(kCcSample);
+        if (n == 0) continue;
+        const uint64_t w0 = pk_off[v];
+        const uint32_t w = pk_width[v];
+        uint32_t x = pk[w0];
+        if (x < V) uf_link(parent, uint32_t(v), x);
+        for (uint32_t r = 1; r < n; ++r) {
+            const uint64_t o = uint64_t(r - 1) * w;
+            const uint64_t wd = w0 + 1 + (o >> 5);
+            const uint32_t sh = uint32_t(o & 31u);
+            uint64_t word = w ? pk[wd] : 0u;
+            if (w && sh + w > 32u) word |= uint64_t(pk[wd + 1]) << 32;
+            x += uint32_t((word >> sh) & ((uint64_t(1) << w) - 1));
+            if (x < V) uf_link(parent, uint32_t(v), x);
+        }
+        edges += n;
+    }
+    edges = wave_sum64(edges);
+    if (lane_id() == 0 && edges) atomicAdd(&ctr[C_EDGES], (unsigned long long)edges);
+}
+
 __global__ void k_compress(uint32_t *parent, uint64_t V) {
     for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
          v += uint64_t(gridDim.x) * blockDim.x) {
@@ -919,13 +1036,28 @@ static void launch_variant(int var, const ScanArgs &s, const OpArgs &a, hipStrea
     }
 }
 
+// Packed lists are scanned by V5 only (their chunks are their blocks).
+template <int A>
+static void launch_packed(const ScanArgs &s, const OpArgs &a, hipStream_t stream) {
+    hipLaunchKernelGGL((k_balanced<PackedCol, A>), dim3(kMaxGrid), dim3(kBlock), 0, stream, s, a);
+}
+
+// Points a scan at the graph's packed lists (no-op for plain lists).
+static void use_packed(ScanArgs &s, const emogi_graph_s *g) {
+    if (!g->packed.stream) return;
+    s.pk = g->packed.stream;
+    s.pk_off = g->packed.off;
+    s.pk_width = g->packed.width;
+    s.align_mask = 0;
+}
+
 // Levels per host wait for BFS: the setting, or (0) 8 on graphs of fewer
 // than 2^24 edges and 1 above (measured on R-MAT 16/18/20: batches win up to
 // scale 18; at scale 20 the ordered per-level frontier is worth more than the
 // saved waits); always 1 when the scheduler needs per-level features or
 // timings.
 static uint32_t level_batch(const emogi_graph_s *g) {
-    if (sched_needs_features(g) || g->sched_mode == EMOGI_SCHED_PROBE) return 1;
+    if (sched_needs_features(g) || g->sched_mode == EMOGI_SCHED_PROBE || g->packed.stream) return 1;
     if (g->level_batch) return g->level_batch;
     return g->E < (uint64_t(1) << 24) ? 8u : 1u;
 }
@@ -1074,6 +1206,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                     s.req_unit = g->request_unit;
                     s.col_bytes = g->col_bytes;
                     s.tier = tier_view(g);
+                    use_packed(s, g);
                     const unsigned nb = unsigned((lo + kScanTile) / kScanTile);
                     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums);
                     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nb);
@@ -1085,11 +1218,16 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                     a.V = uint32_t(V);
                     a.ctr = p.counters;
                     a.split = 0xFFFFFFFFu;
-                    if (g->col_bytes == 8)
+                    if (g->packed.stream)
+                        launch_packed<A_LINK>(s, a, stream);
+                    else if (g->col_bytes == 8)
                         launch_variant<uint64_t, A_LINK>(EMOGI_V5_BALANCED, s, a, stream);
                     else
                         launch_variant<uint32_t, A_LINK>(EMOGI_V5_BALANCED, s, a, stream);
                 }
+            } else if (g->packed.stream) {
+                hipLaunchKernelGGL(k_cc_sample_packed, dim3(kMaxGrid), dim3(kBlock), 0, stream, g->row_ptr,
+                                   g->packed.stream, g->packed.off, g->packed.width, V, out, p.counters);
             } else if (g->col_bytes == 8) {
                 hipLaunchKernelGGL(k_cc_sample<uint64_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, g->row_ptr,
                                    static_cast<const uint64_t *>(g->col), V, tier_view(g), out, p.counters);
@@ -1158,6 +1296,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     int cur = 0;
     uint32_t iter = 0;
     bool overflow_seen = false;
+    uint64_t packed_bytes = 0;  // encoded bytes of the packed lists scanned
     // The next frontier is listed from a bitmap (ordered) for BFS and CC label
     // propagation when asked, and always for SSSP, whose marks also hold the
     // improved vertices that wait for a later distance band.
@@ -1358,6 +1497,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             s.col_bytes = g->col_bytes;
             s.chunk_scan = nullptr;
             s.tier = tier_view(g);
+            use_packed(s, g);
             OpArgs a;
             a.state = out;
             a.bitmap = p.bitmap;
@@ -1383,8 +1523,12 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 s.chunk_scan = p.chunk_scan;
             }
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
-            const int key = kalgo * 2 + (g->col_bytes == 8 ? 1 : 0);
+            const int key = g->packed.stream ? 8 + kalgo : kalgo * 2 + (g->col_bytes == 8 ? 1 : 0);
             switch (key) {
+            case 8 + A_BFS: launch_packed<A_BFS>(s, a, stream); break;
+            case 8 + A_SSSP: launch_packed<A_SSSP>(s, a, stream); break;
+            case 8 + A_CC: launch_packed<A_CC>(s, a, stream); break;
+            case 8 + A_LINK: launch_packed<A_LINK>(s, a, stream); break;
             case 0: launch_variant<uint32_t, A_BFS>(v, s, a, stream); break;
             case 1: launch_variant<uint64_t, A_BFS>(v, s, a, stream); break;
             case 2: launch_variant<uint32_t, A_SSSP>(v, s, a, stream); break;
@@ -1420,7 +1564,8 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             return EMOGI_E_HIP;
         }
         if (want_feats) memcpy(S.level_features[iter], feats, sizeof(feats));
-        if (g->sched_mode == EMOGI_SCHED_PROBE) {
+        if (g->packed.stream) var = EMOGI_V5_BALANCED;  // the one variant that decodes packed lists
+        if (g->sched_mode == EMOGI_SCHED_PROBE && !g->packed.stream) {
             // Time every variant on the same level state, then run the fastest.
             if ((st = snapshot(g, algo, out, stream, false)) != EMOGI_OK) return st;
             float best = 1e30f;
@@ -1455,6 +1600,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         S.request_bytes += hc[C_REQBYTES];
         S.vertices_expanded += hc[C_VERTS];
         S.weights_read += hc[C_WLINK];
+        packed_bytes += hc[C_PKBYTES];
         if (hc[C_OVERFLOW]) overflow_seen = true;
         n = hc[C_NEXT];
         if (identity) {
@@ -1468,8 +1614,10 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     if (kalgo == A_LINK)
         hipLaunchKernelGGL(k_compress, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
     S.iterations = iter;
-    // ids of every list read over the link; SSSP weights only where read
-    S.useful_link_bytes = (S.edges_scanned - S.tier_edges) * g->col_bytes + S.weights_read * 4;
+    // ids of every list read over the link (packed: their encoded bytes);
+    // SSSP weights only where read
+    S.useful_link_bytes = (g->packed.stream ? packed_bytes : (S.edges_scanned - S.tier_edges) * g->col_bytes) +
+                          S.weights_read * 4;
     if (overflow_seen) {
         EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
                       EMOGI_E_HIP);
@@ -1520,6 +1668,7 @@ static emogi_status_t pagerank(emogi_graph_s *g, uint32_t iters, uint32_t F, uin
     emogi_stats_t &S = g->stats;
     memset(&S, 0, sizeof(S));
     S.request_unit = g->request_unit;
+    uint64_t packed_bytes = 0;
     EMOGI_HIP_TRY(hipEventRecord(g->ev_begin, stream), EMOGI_E_HIP);
     if (V > 0) {
         for (void **b : {reinterpret_cast<void **>(&p.pr_acc), reinterpret_cast<void **>(&p.pr_contrib)})
@@ -1543,6 +1692,7 @@ static emogi_status_t pagerank(emogi_graph_s *g, uint32_t iters, uint32_t F, uin
         s.req_unit = g->request_unit;
         s.col_bytes = g->col_bytes;
         s.tier = tier_view(g);
+        use_packed(s, g);
         const unsigned nb = unsigned((V + kScanTile) / kScanTile);
         hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums);
         hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nb);
@@ -1555,7 +1705,9 @@ static emogi_status_t pagerank(emogi_graph_s *g, uint32_t iters, uint32_t F, uin
         for (uint32_t t = 0; t < iters; ++t) {
             EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
-            if (g->col_bytes == 8)
+            if (g->packed.stream)
+                hipLaunchKernelGGL(k_pr_pull<PackedCol>, dim3(kMaxGrid), dim3(kBlock), 0, stream, s, pa);
+            else if (g->col_bytes == 8)
                 hipLaunchKernelGGL(k_pr_pull<uint64_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, s, pa);
             else
                 hipLaunchKernelGGL(k_pr_pull<uint32_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, s, pa);
@@ -1584,10 +1736,11 @@ static emogi_status_t pagerank(emogi_graph_s *g, uint32_t iters, uint32_t F, uin
             S.tier_edges += hc[C_TIER];
             S.request_bytes += hc[C_REQBYTES];
             S.vertices_expanded += hc[C_VERTS];
+            packed_bytes += hc[C_PKBYTES];
         }
     }
     S.iterations = iters;
-    S.useful_link_bytes = (S.edges_scanned - S.tier_edges) * g->col_bytes;
+    S.useful_link_bytes = g->packed.stream ? packed_bytes : (S.edges_scanned - S.tier_edges) * g->col_bytes;
     EMOGI_HIP_TRY(hipEventRecord(g->ev_end, stream), EMOGI_E_HIP);
     EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
     float total = 0.f;

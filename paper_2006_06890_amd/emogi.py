@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libemogi.so")
 
 PLACEMENTS = {"hbm": 0, "host_zero_copy": 1, "managed": 2}
-F_SYMMETRIC, F_VALIDATE, F_BORROW, F_PIN_NONCOHERENT = 0x1, 0x2, 0x4, 0x8
+F_SYMMETRIC, F_VALIDATE, F_BORROW, F_PIN_NONCOHERENT, F_PACK = 0x1, 0x2, 0x4, 0x8, 0x10
 SCHED_HEURISTIC, SCHED_LEARNED, SCHED_PROBE, SCHED_RECORD = 16, 17, 18, 0x100
 VARIANTS = ["V0_thread", "V1_group16", "V2_wave", "V3_wave_aligned", "V4_block", "V5_balanced"]
 N_SCHED_PARAMS = 5638
@@ -188,6 +188,7 @@ def lib():
             "emogi_host_free": (i32, [p]),
             "emogi_graph_create": (i32, [p, u64, p, u32, p, i32, u32, ctypes.POINTER(ctypes.c_void_p)]),
             "emogi_graph_destroy": (i32, [p]),
+            "emogi_packed_bytes": (i32, [p, ctypes.POINTER(ctypes.c_uint64)]),
             "emogi_set_request_unit": (i32, [p, u32]),
             "emogi_set_scheduler": (i32, [p, i32]),
             "emogi_set_sssp_delta": (i32, [p, u32]),
@@ -287,11 +288,13 @@ class Graph:
 
     row_ptr: uint64[V+1]; col: uint32|uint64[E] (numpy or PinnedArray);
     weights: uint32[E] or None.  With ``borrow`` the edge arrays must be
-    PinnedArray objects and are used in place (host zero-copy only).
+    PinnedArray objects and are used in place (host zero-copy only).  With
+    ``pack`` the lists (ascending) are stored compressed and col is read only
+    here (``EMOGI_F_PACK``).
     """
 
     def __init__(self, row_ptr, col, weights=None, placement="host_zero_copy",
-                 symmetric=False, validate=False, borrow=False, noncoherent=False):
+                 symmetric=False, validate=False, borrow=False, noncoherent=False, pack=False):
         rp = np.ascontiguousarray(row_ptr, dtype=np.uint64)
         col_arr = col.array if isinstance(col, PinnedArray) else np.ascontiguousarray(col)
         if col_arr.dtype not in (np.uint32, np.uint64):
@@ -302,7 +305,8 @@ class Graph:
             col = col_arr
         self._keep = (rp, col, weights)
         flags = ((F_SYMMETRIC if symmetric else 0) | (F_VALIDATE if validate else 0)
-                 | (F_BORROW if borrow else 0) | (F_PIN_NONCOHERENT if noncoherent else 0))
+                 | (F_BORROW if borrow else 0) | (F_PIN_NONCOHERENT if noncoherent else 0)
+                 | (F_PACK if pack else 0))
         h = ctypes.c_void_p()
         V = rp.shape[0] - 1
         check(lib().emogi_graph_create(rp.ctypes.data, V, _addr(col), col_arr.dtype.itemsize,
@@ -315,6 +319,12 @@ class Graph:
         self.placement = placement
         if not borrow:
             self._keep = None  # copied by the library
+
+    def packed_bytes(self):
+        """Bytes of the packed lists (0 unless created with ``pack``)."""
+        b = ctypes.c_uint64()
+        check(lib().emogi_packed_bytes(self._h, ctypes.byref(b)))
+        return b.value
 
     # -- configuration -------------------------------------------------------
     def set_variant(self, v):

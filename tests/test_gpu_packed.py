@@ -1,0 +1,169 @@
+"""Packed neighbour lists (EMOGI_F_PACK): the compression with decoding on
+the GPU that Sec. 6 proposes.  Packing changes how the lists travel, never
+what a traversal computes, so BFS levels, SSSP distances, CC labels and
+PageRank scores over packed lists must equal the oracle's on the plain lists
+bit for bit; the encoded size is checked against the block format written
+out here from its definition."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _graphs():
+    gs = {
+        "rmat13": graphgen.rmat(13, seed=7).to_csr(4, weights=True),
+        "uniform11": graphgen.uniform(11, 2 ** 11 * 8, seed=2).to_csr(4, weights=True),
+        "path300": graphgen.path(300),
+        "star5000": graphgen.star(5000),       # a list of 4999 ids: 79 blocks
+        "cliques": graphgen.disjoint_cliques([1, 2, 3, 64, 65, 129, 5, 1]),  # block edges
+        "grid20": graphgen.grid(20),
+        "edgeless7": graphgen.edgeless(7),
+        "single": graphgen.edgeless(1),
+        "pair": graphgen.path(2),
+    }
+    rng = np.random.Generator(np.random.PCG64(5))
+    e = rng.integers(0, 3000, size=(20000, 2))
+    gs["directed"] = graphgen.from_edges(3000, e, symmetric=False, weights=rng.integers(1, 256, size=20000))
+    e = rng.integers(0, 500, size=(6000, 2))
+    gs["multi"] = graphgen.from_edges(500, e, symmetric=True, simple=False,   # repeated ids: zero gaps
+                                      weights=rng.integers(1, 256, size=6000))
+    for g in gs.values():
+        if g.weights is None:
+            g.weights = graphgen.pair_weights(g, seed=3)
+    return gs
+
+
+GRAPHS = _graphs()
+SYMMETRIC = {k: k != "directed" for k in GRAPHS}
+
+
+def _packed_words(rp, col):
+    """Words of each list: blocks of 64 ids, each its first id (one word)
+    and the gaps to its other ids at the list's width w (the bit length of
+    the largest gap inside any of its blocks), packed into
+    ceil((count - 1) * w / 32) words."""
+    V = rp.shape[0] - 1
+    words = np.zeros(V, dtype=np.int64)
+    for u in range(V):
+        ids = [int(x) for x in col[int(rp[u]):int(rp[u + 1])]]
+        blocks = [ids[k:k + 64] for k in range(0, len(ids), 64)]
+        w = max((b[i + 1] - b[i] for b in blocks for i in range(len(b) - 1)), default=0).bit_length()
+        words[u] = sum(1 + ((len(b) - 1) * w + 31) // 32 for b in blocks)
+    return words
+
+
+def _sources(g):
+    deg = g.degrees()
+    nz = np.flatnonzero(deg > 0)
+    s = {0, g.num_vertices - 1}
+    if nz.shape[0]:
+        s |= {int(nz[0]), int(nz[nz.shape[0] // 2]), int(np.argmax(deg))}
+    return sorted(s)
+
+
+@pytest.mark.parametrize("placement", ["host_zero_copy", "hbm"])
+@pytest.mark.parametrize("col_bytes", [4, 8])
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+def test_packed_traversals_match_oracle(gpu_device, name, col_bytes, placement):
+    import torch
+    import paper_2006_06890_amd as E
+    g = GRAPHS[name]
+    col = g.col.astype(np.uint32 if col_bytes == 4 else np.uint64)
+    out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+    with E.Graph(g.row_ptr, col, g.weights, placement=placement, symmetric=SYMMETRIC[name], pack=True) as G:
+        assert G.packed_bytes() == 4 * int(_packed_words(g.row_ptr, g.col).sum())
+        for s in _sources(g):
+            for ordered in (True, False):
+                G.set_frontier_order(ordered)
+                G.bfs(s, out)
+                np.testing.assert_array_equal(E.to_u32(out), oracle.bfs(g.row_ptr, g.col, s),
+                                              err_msg=f"bfs {name} s{s} ordered={ordered}")
+            for delta in (0, 3, 1000):
+                G.set_sssp_delta(delta)
+                G.sssp(s, out)
+                np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(g.row_ptr, g.col, g.weights, s),
+                                              err_msg=f"sssp {name} s{s} delta {delta}")
+        if SYMMETRIC[name]:
+            exp = oracle.cc(g.row_ptr, g.col)
+            for algo in ("sampled_union_find", "label_propagation"):
+                G.set_cc_algorithm(algo)
+                G.cc(out)
+                np.testing.assert_array_equal(E.to_u32(out), exp, err_msg=f"cc {algo} {name}")
+            F, it = 40, 3
+            d = (85 << F) // 100
+            np.testing.assert_array_equal(E.to_u64(G.pagerank(it, F, d))[: g.num_vertices],
+                                          oracle.pagerank(g.row_ptr, g.col, F, d, it), err_msg=f"pr {name}")
+
+
+def test_packed_link_bytes(gpu_device):
+    """A BFS that reaches every vertex scans each list once, so its link
+    bytes are the whole encoding; the encoding of a random-id R-MAT graph is
+    well under its 4-byte ids."""
+    import torch
+    import paper_2006_06890_amd as E
+    g = GRAPHS["rmat13"]
+    words = _packed_words(g.row_ptr, g.col)
+    out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+    with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True, pack=True) as G:
+        s = int(np.argmax(g.degrees()))
+        G.bfs(s, out)
+        lv = E.to_u32(out)
+        reached = lv != 0xFFFFFFFF
+        st = G.stats()
+        assert st["edges_scanned"] == int(g.degrees()[reached].sum())
+        assert st["useful_link_bytes"] == 4 * int(words[reached].sum())
+        assert st["request_bytes"] >= st["useful_link_bytes"]
+        assert G.packed_bytes() < 0.75 * 4 * g.num_edges
+        assert set(st["level_variant"]) == {5}
+
+
+def test_packed_wide_gaps(gpu_device):
+    """Ids spread over 2^25 vertices: gap widths of 20-25 bits, so gaps
+    straddle words in every way; lists of 1, 63, 64, 65 and 300 ids."""
+    import torch
+    import paper_2006_06890_amd as E
+    V = (1 << 25) + 5
+    rng = np.random.Generator(np.random.PCG64(11))
+    edges = []
+    hubs = [0, 17, V - 1, 1 << 24]
+    for h, k in zip(hubs, (300, 65, 64, 63)):
+        for v in rng.choice(V, size=k, replace=False):
+            edges.append((h, int(v)))
+    edges.append((5, V - 2))
+    g = graphgen.from_edges(V, np.array(edges), symmetric=True,
+                            weights=rng.integers(1, 1 << 20, size=len(edges)))
+    out = torch.empty(V, dtype=torch.int32, device="cuda")
+    with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True, pack=True) as G:
+        nz = np.flatnonzero(g.degrees() > 0)
+        words = np.zeros(V, dtype=np.int64)
+        words[nz] = _packed_words(np.concatenate([[0], np.cumsum(g.degrees()[nz])]).astype(np.uint64),
+                                  g.col)
+        assert G.packed_bytes() == 4 * int(words.sum())
+        for s in (0, int(nz[len(nz) // 2]), V - 1, 3):
+            G.bfs(s, out)
+            np.testing.assert_array_equal(E.to_u32(out), oracle.bfs(g.row_ptr, g.col, s), err_msg=f"bfs s{s}")
+            G.sssp(s, out)
+            np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(g.row_ptr, g.col, g.weights, s),
+                                          err_msg=f"sssp s{s}")
+        G.cc(out)
+        np.testing.assert_array_equal(E.to_u32(out), oracle.cc(g.row_ptr, g.col))
+
+
+def test_packed_rejects(gpu_device):
+    import paper_2006_06890_amd as E
+    rp = np.array([0, 2, 3, 4], dtype=np.uint64)
+    col = np.array([2, 1, 0, 0], dtype=np.uint32)   # vertex 0's list descends
+    with pytest.raises(E.EmogiError) as ex:
+        E.Graph(rp, col, pack=True)
+    assert ex.value.code == -1
+    g = GRAPHS["rmat13"]
+    with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True, pack=True) as G:
+        for call in (lambda: G.bfs_batch([0, 1]), lambda: G.sssp_batch([0, 1]),
+                     lambda: G.set_hbm_tier(1 << 20)):
+            with pytest.raises(E.EmogiError) as ex:
+                call()
+            assert ex.value.code == -8
