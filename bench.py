@@ -415,6 +415,33 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             }
             H.close()
             log(f"[bench] arm {placement}: {arms[placement]}")
+    if not args.no_arms:
+        # packed lists (the compression Sec. 6 proposes): the same graph with
+        # ids and weights bit-packed per list, every source of the step
+        t0 = time.perf_counter()
+        P = E.Graph(rp, col, w, symmetric=True, borrow=True, pack=True)
+        create_s = time.perf_counter() - t0
+        P.set_scheduler("heuristic")
+        ids_b, w_b = P.packed_bytes()
+        ms_a, edges, tot_ms, link = {}, 0, 0.0, {}
+        for s in sources:
+            r = run_step(P, s, out, args.algos)
+            reached = r["bfs"]["edges_scanned"]
+            for a in r:
+                ms_a[a] = ms_a.get(a, 0.0) + r[a]["total_ms"]
+                link[a] = link.get(a, 0) + r[a]["useful_link_bytes"]
+                edges += M if a == "cc" else reached
+                tot_ms += r[a]["total_ms"]
+        arms["packed"] = {
+            "ids_GB": round(ids_b / 1e9, 2), "weights_GB": round(w_b / 1e9, 2),
+            "id_bytes_per_edge": round(ids_b / M, 3), "weight_bytes_per_edge": round(w_b / M, 3),
+            "create_s": round(create_s, 1),
+            "gteps": round(edges / (tot_ms * 1e6), 4),
+            **{f"{a}_ms": round(ms_a[a] / len(sources), 2) for a in ms_a},
+            **{f"{a}_link_GB": round(link[a] / len(sources) / 1e9, 2) for a in link},
+        }
+        P.close()
+        log(f"[bench] arm packed: {arms['packed']}")
     if arms:
         result["arms"] = arms
     return result

@@ -96,14 +96,15 @@ typedef struct {
     uint64_t edges_scanned;      /* sum of their out-degrees (re-expansions included)    */
     uint64_t useful_link_bytes;  /* (edges_scanned - tier_edges) * col_bytes
                                     + 4 * weights_read: bytes the lists need from the link
-                                    (packed graphs: the encoded bytes of the lists scanned
-                                    + 4 * weights_read)                                     */
+                                    (packed graphs: the encoded bytes of the lists scanned,
+                                    and of their weights for SSSP)                          */
     uint64_t request_bytes;      /* the same lists rounded out to the request unit R     */
     uint64_t tier_edges;         /* of edges_scanned, those read from the HBM tier       */
     uint64_t weights_read;       /* SSSP: weights read over the host link (a weight is
                                     read only when its edge could improve the target:
                                     dist(v) > dist(u) + the smallest weight into v,
-                                    or into any vertex when the edges are in HBM)     */
+                                    or into any vertex when the edges are in HBM;
+                                    0 on packed graphs, whose weights come packed)    */
     double total_ms;             /* whole traversal, HIP events on the caller's stream   */
     double expand_ms;            /* sum of the neighbour-scan kernels alone              */
     uint32_t expand_launches;    /* how many neighbour-scan kernels ran                  */
@@ -164,19 +165,23 @@ emogi_status_t emogi_host_free(void *p);
  * decoding on the GPU that Sec. 6 proposes to cut link traffic: each list
  * (ascending ids required, else EMOGI_E_INVALID) is cut into blocks of 64
  * ids, a block being its first id as a 32-bit word and then the gaps to the
- * next ids bit-packed at the list's gap width.  The blocks go where the
- * placement puts the lists; col is read only during creation; weights stay
- * as given.  BFS, SSSP, CC and PageRank scan packed lists with the
- * edge-balanced variant (V5) whatever the scheduler; batched traversal and
- * the HBM tier are EMOGI_E_UNSUPPORTED on packed graphs.
+ * next ids bit-packed at the list's gap width; a list's weights are
+ * bit-packed at the list's weight width (the bit length of its largest
+ * weight) in a second stream.  Both go where the placement puts the lists;
+ * col and weights are read only during creation.  BFS, SSSP, CC and
+ * PageRank scan packed lists with the edge-balanced variant (V5) whatever
+ * the scheduler; SSSP then reads each scanned list's packed weights whole.
+ * Batched traversal and the HBM tier are EMOGI_E_UNSUPPORTED on packed
+ * graphs.
  * Nothing is leaked on failure; *out is set only on success. */
 emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t num_vertices,
                                   const void *col, uint32_t col_bytes,
                                   const uint32_t *weights, emogi_placement_t placement,
                                   uint32_t flags, emogi_graph_t *out);
 emogi_status_t emogi_graph_destroy(emogi_graph_t g);
-/* Bytes of the packed lists (0 for a graph created without EMOGI_F_PACK). */
-emogi_status_t emogi_packed_bytes(emogi_graph_t g, uint64_t *bytes);
+/* Bytes of the packed ids and of the packed weights (weight_bytes may be
+ * NULL); both 0 for a graph created without EMOGI_F_PACK. */
+emogi_status_t emogi_packed_bytes(emogi_graph_t g, uint64_t *id_bytes, uint64_t *weight_bytes);
 
 /* Request unit R (bytes, power of two 32..4096) used to round list starts
  * down (Sec. 4.3.2).  Default 256: the smallest block that runs the MI355X

@@ -120,8 +120,14 @@ static void release(emogi_graph_s *g) {
     free_edges(g->weights, g->w_kind);
     if (g->row_ptr) (void)hipFree(g->row_ptr);
     if (g->in_min) (void)hipFree(g->in_min);
-    if (g->packed.on_device && g->packed.stream) (void)hipFree(g->packed.stream);
+    if (g->packed.on_device) {
+        if (g->packed.stream) (void)hipFree(g->packed.stream);
+        if (g->packed.wstream) (void)hipFree(g->packed.wstream);
+    }
     if (g->packed.pinned) (void)hipHostFree(g->packed.pinned);
+    if (g->packed.wpinned) (void)hipHostFree(g->packed.wpinned);
+    if (g->packed.woff) (void)hipFree(g->packed.woff);
+    if (g->packed.wwidth) (void)hipFree(g->packed.wwidth);
     if (g->packed.off) (void)hipFree(g->packed.off);
     if (g->packed.width) (void)hipFree(g->packed.width);
     Pool &p = g->pool;
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(256) void k_in_min_pack(const uint32_t *m, uint64_t
 // Per-vertex smallest incoming weight (uint8, saturated) for SSSP's
 // weight-read skipping; computed from the edges, so it holds for directed
 // graphs and asymmetric weights alike.
-static emogi_status_t compute_in_min(emogi_graph_s *g, const void *col_host) {
+static emogi_status_t compute_in_min(emogi_graph_s *g) {
     const uint64_t V = g->V, E = g->E;
     uint32_t *m = nullptr;
     if (hipMalloc(&m, V * sizeof(uint32_t)) != hipSuccess) {
@@ -205,35 +211,14 @@ static emogi_status_t compute_in_min(emogi_graph_s *g, const void *col_host) {
     }
     const unsigned grid = 256u * 8u;
     hipLaunchKernelGGL(k_in_min_init, dim3(grid), dim3(256), 0, nullptr, m, V);
-    auto run = [&](const void *c, const uint32_t *w, uint64_t n) {
-        if (g->col_bytes == 8)
-            hipLaunchKernelGGL(k_in_min<uint64_t>, dim3(grid), dim3(256), 0, nullptr,
-                               static_cast<const uint64_t *>(c), w, n, V, m);
-        else
-            hipLaunchKernelGGL(k_in_min<uint32_t>, dim3(grid), dim3(256), 0, nullptr,
-                               static_cast<const uint32_t *>(c), w, n, V, m);
-    };
-    hipError_t e0 = hipSuccess;
-    if (g->col) {
-        run(g->col, g->weights, E);
-    } else {
-        // a packed graph keeps no id array the GPU can read: stage slices of
-        // the caller's ids in GPU memory (null-stream order keeps the slice
-        // buffer from being overwritten while a kernel still reads it)
-        const uint64_t slice = uint64_t(1) << 26;
-        void *stage = nullptr;
-        e0 = hipMalloc(&stage, std::min(slice, E) * g->col_bytes);
-        for (uint64_t i0 = 0; e0 == hipSuccess && i0 < E; i0 += slice) {
-            const uint64_t n = std::min(slice, E - i0);
-            e0 = hipMemcpy(stage, static_cast<const char *>(col_host) + i0 * g->col_bytes, n * g->col_bytes,
-                           hipMemcpyHostToDevice);
-            if (e0 == hipSuccess) run(stage, g->weights + i0, n);
-        }
-        (void)hipDeviceSynchronize();
-        if (stage) (void)hipFree(stage);
-    }
+    if (g->col_bytes == 8)
+        hipLaunchKernelGGL(k_in_min<uint64_t>, dim3(grid), dim3(256), 0, nullptr,
+                           static_cast<const uint64_t *>(g->col), g->weights, E, V, m);
+    else
+        hipLaunchKernelGGL(k_in_min<uint32_t>, dim3(grid), dim3(256), 0, nullptr,
+                           static_cast<const uint32_t *>(g->col), g->weights, E, V, m);
     hipLaunchKernelGGL(k_in_min_pack, dim3(grid), dim3(256), 0, nullptr, m, V, g->in_min);
-    const hipError_t e1 = e0 != hipSuccess ? e0 : hipGetLastError();
+    const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipDeviceSynchronize();
     (void)hipFree(m);
     if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -244,23 +229,86 @@ static emogi_status_t compute_in_min(emogi_graph_s *g, const void *col_host) {
     return EMOGI_OK;
 }
 
-// EMOGI_F_PACK: encodes the lists on the host threads in two passes over col
-// (gap widths and word counts, then the blocks) straight into the stream's
-// final host memory (pinned) or a host buffer copied to HBM.
-static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, const void *col) {
+// Allocates one packed stream where the placement puts the lists: pinned
+// host memory written in place, or a host buffer that is copied to HBM later.
+static emogi_status_t alloc_stream(emogi_graph_s *g, size_t bytes, void **pinned, uint32_t **host,
+                                   std::vector<uint32_t> &staging) {
+    if (g->placement == EMOGI_PLACE_HOST_ZERO_COPY) {
+        unsigned fl = hipHostMallocMapped;
+        if (g->flags & EMOGI_F_PIN_NONCOHERENT) fl |= hipHostMallocNonCoherent;
+        if (hipHostMalloc(pinned, bytes, fl) != hipSuccess) {
+            (void)hipGetLastError();
+            *pinned = nullptr;
+            set_error("hipHostMalloc of %zu pinned bytes for the packed lists failed", bytes);
+            return EMOGI_E_OOM_HOST;
+        }
+        *host = static_cast<uint32_t *>(*pinned);
+    } else {
+        staging.resize(bytes / 4);
+        *host = staging.data();
+    }
+    return EMOGI_OK;
+}
+
+// The GPU's view of a stream built by alloc_stream (copied to HBM if placed there).
+static emogi_status_t publish_stream(emogi_graph_s *g, size_t bytes, void *pinned, const uint32_t *host,
+                                     uint32_t **dev) {
+    void *d = nullptr;
+    if (g->placement == EMOGI_PLACE_HOST_ZERO_COPY) {
+        EMOGI_HIP_TRY(hipHostGetDevicePointer(&d, pinned, 0), EMOGI_E_HIP);
+    } else {
+        if (hipMalloc(&d, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of %zu bytes for the packed lists failed", bytes);
+            return EMOGI_E_OOM_DEVICE;
+        }
+        *dev = static_cast<uint32_t *>(d);
+        EMOGI_HIP_TRY(hipMemcpy(d, host, bytes, hipMemcpyHostToDevice), EMOGI_E_HIP);
+    }
+    *dev = static_cast<uint32_t *>(d);
+    return EMOGI_OK;
+}
+
+// Appends `w`-bit fields to a word stream.
+struct BitWriter {
+    uint32_t *o;
+    uint64_t acc = 0;
+    uint32_t nbits = 0;
+    void put(uint64_t x, uint32_t w) {  // x < 2^w, w <= 32; nbits < 32 before
+        acc |= x << nbits;
+        nbits += w;
+        if (nbits >= 32) {
+            *o++ = uint32_t(acc);
+            acc >>= 32;
+            nbits -= 32;
+        }
+    }
+    void flush() {
+        if (nbits) *o++ = uint32_t(acc);
+        acc = 0;
+        nbits = 0;
+    }
+};
+
+// EMOGI_F_PACK: encodes the lists (and weights) on the host threads in two
+// passes over col: widths and word counts, then the blocks, straight into
+// the streams' final host memory (pinned) or host buffers copied to HBM.
+static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, const void *col,
+                                 const uint32_t *weights) {
     const uint64_t V = g->V;
     const uint32_t cb = g->col_bytes;
     if (g->placement == EMOGI_PLACE_MANAGED) {
         set_error("packed lists are placed in pinned host memory or HBM, not managed memory");
         return EMOGI_E_UNSUPPORTED;
     }
-    std::vector<uint8_t> width(V);
-    std::vector<uint64_t> off(V + 1, 0);
+    std::vector<uint8_t> width(V), wwidth(weights ? V : 0);
+    std::vector<uint64_t> off(V + 1, 0), woff(weights ? V + 1 : 0, 0);
     std::atomic<uint64_t> bad{~uint64_t(0)};
     parallel_for(V, [&](uint64_t u0, uint64_t u1) {
         for (uint64_t u = u0; u < u1; ++u) {
             const uint64_t b = row_ptr[u], e = row_ptr[u + 1];
             uint64_t maxgap = 0, prev = 0;
+            uint32_t maxw = 0;
             for (uint64_t i = b; i < e; ++i) {
                 const uint64_t x = col_at(col, cb, i);
                 if (x > 0xFFFFFFFFull || (i > b && x < prev)) {
@@ -270,6 +318,7 @@ static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, cons
                 }
                 if ((i - b) % 64 != 0 && x >= prev) maxgap = std::max(maxgap, x - prev);
                 prev = x;
+                if (weights) maxw = std::max(maxw, weights[i]);
             }
             const uint32_t w = maxgap ? 64u - uint32_t(__builtin_clzll(maxgap)) : 0u;
             width[u] = uint8_t(w);
@@ -277,6 +326,11 @@ static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, cons
             if (d) {
                 const uint64_t nb = (d + 63) / 64, last = d - (nb - 1) * 64;
                 off[u + 1] = (nb - 1) * (1 + (63 * uint64_t(w) + 31) / 32) + 1 + ((last - 1) * w + 31) / 32;
+            }
+            if (weights) {
+                const uint32_t ww = maxw ? 32u - uint32_t(__builtin_clz(maxw)) : 0u;
+                wwidth[u] = uint8_t(ww);
+                woff[u + 1] = (d * ww + 31) / 32;
             }
         }
     });
@@ -286,75 +340,60 @@ static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, cons
         return EMOGI_E_INVALID;
     }
     for (uint64_t u = 0; u < V; ++u) off[u + 1] += off[u];
-    const uint64_t words = off[V];
-    const size_t bytes = std::max<size_t>(8, words * 4);
-    uint32_t *host = nullptr;
-    std::vector<uint32_t> staging;
+    if (weights)
+        for (uint64_t u = 0; u < V; ++u) woff[u + 1] += woff[u];
     Packed &pk = g->packed;
-    if (g->placement == EMOGI_PLACE_HOST_ZERO_COPY) {
-        unsigned fl = hipHostMallocMapped;
-        if (g->flags & EMOGI_F_PIN_NONCOHERENT) fl |= hipHostMallocNonCoherent;
-        void *h = nullptr;
-        if (hipHostMalloc(&h, bytes, fl) != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("hipHostMalloc of %zu pinned bytes for the packed lists failed", bytes);
-            return EMOGI_E_OOM_HOST;
-        }
-        pk.pinned = h;
-        host = static_cast<uint32_t *>(h);
-    } else {
-        staging.resize(bytes / 4);
-        host = staging.data();
-    }
+    const uint64_t words = off[V], wwords = weights ? woff[V] : 0;
+    const size_t bytes = std::max<size_t>(8, words * 4), wbytes = std::max<size_t>(8, wwords * 4);
+    uint32_t *host = nullptr, *whost = nullptr;
+    std::vector<uint32_t> staging, wstaging;
+    emogi_status_t st = alloc_stream(g, bytes, &pk.pinned, &host, staging);
+    if (st == EMOGI_OK && weights) st = alloc_stream(g, wbytes, &pk.wpinned, &whost, wstaging);
+    if (st != EMOGI_OK) return st;
     parallel_for(V, [&](uint64_t u0, uint64_t u1) {
         for (uint64_t u = u0; u < u1; ++u) {
             const uint64_t b = row_ptr[u], e = row_ptr[u + 1];
             const uint32_t w = width[u];
-            uint32_t *o = host + off[u];
+            BitWriter bw{host + off[u]};
             for (uint64_t k0 = b; k0 < e; k0 += 64) {
                 const uint64_t k1 = std::min(e, k0 + 64);
-                uint64_t prev = col_at(col, cb, k0), acc = 0;
-                uint32_t nbits = 0;
-                *o++ = uint32_t(prev);
+                uint64_t prev = col_at(col, cb, k0);
+                *bw.o++ = uint32_t(prev);
                 for (uint64_t i = k0 + 1; i < k1; ++i) {
                     const uint64_t x = col_at(col, cb, i);
-                    acc |= (x - prev) << nbits;  // nbits < 32 and gap < 2^w, w <= 32
-                    nbits += w;
+                    bw.put(x - prev, w);
                     prev = x;
-                    if (nbits >= 32) {
-                        *o++ = uint32_t(acc);
-                        acc >>= 32;
-                        nbits -= 32;
-                    }
                 }
-                if (nbits) *o++ = uint32_t(acc);
+                bw.flush();
+            }
+            if (weights) {
+                BitWriter ws{whost + woff[u]};
+                for (uint64_t i = b; i < e; ++i) ws.put(weights[i], wwidth[u]);
+                ws.flush();
             }
         }
     });
     pk.words = words;
-    if (g->placement == EMOGI_PLACE_HOST_ZERO_COPY) {
-        void *d = nullptr;
-        EMOGI_HIP_TRY(hipHostGetDevicePointer(&d, pk.pinned, 0), EMOGI_E_HIP);
-        pk.stream = static_cast<uint32_t *>(d);
-    } else {
-        void *d = nullptr;
-        if (hipMalloc(&d, bytes) != hipSuccess) {
+    pk.wwords = wwords;
+    if ((st = publish_stream(g, bytes, pk.pinned, host, &pk.stream)) != EMOGI_OK) return st;
+    if (g->placement != EMOGI_PLACE_HOST_ZERO_COPY) pk.on_device = true;
+    if (weights && (st = publish_stream(g, wbytes, pk.wpinned, whost, &pk.wstream)) != EMOGI_OK) return st;
+    auto upload = [&](void **dst, const void *src, size_t n) -> emogi_status_t {
+        if (hipMalloc(dst, std::max<size_t>(n, 8)) != hipSuccess) {
             (void)hipGetLastError();
-            set_error("hipMalloc of %zu bytes for the packed lists failed", bytes);
+            *dst = nullptr;
+            set_error("hipMalloc of the packed list offsets failed");
             return EMOGI_E_OOM_DEVICE;
         }
-        pk.stream = static_cast<uint32_t *>(d);
-        pk.on_device = true;
-        EMOGI_HIP_TRY(hipMemcpy(d, host, bytes, hipMemcpyHostToDevice), EMOGI_E_HIP);
+        if (n) EMOGI_HIP_TRY(hipMemcpy(*dst, src, n, hipMemcpyHostToDevice), EMOGI_E_HIP);
+        return EMOGI_OK;
+    };
+    if ((st = upload(reinterpret_cast<void **>(&pk.off), off.data(), (V + 1) * 8)) != EMOGI_OK) return st;
+    if ((st = upload(reinterpret_cast<void **>(&pk.width), width.data(), V)) != EMOGI_OK) return st;
+    if (weights) {
+        if ((st = upload(reinterpret_cast<void **>(&pk.woff), woff.data(), (V + 1) * 8)) != EMOGI_OK) return st;
+        if ((st = upload(reinterpret_cast<void **>(&pk.wwidth), wwidth.data(), V)) != EMOGI_OK) return st;
     }
-    if (hipMalloc(&pk.off, (V + 1) * sizeof(uint64_t)) != hipSuccess ||
-        hipMalloc(&pk.width, std::max<uint64_t>(V, 1)) != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("hipMalloc of the packed list offsets failed");
-        return EMOGI_E_OOM_DEVICE;
-    }
-    EMOGI_HIP_TRY(hipMemcpy(pk.off, off.data(), (V + 1) * sizeof(uint64_t), hipMemcpyHostToDevice), EMOGI_E_HIP);
-    if (V) EMOGI_HIP_TRY(hipMemcpy(pk.width, width.data(), V, hipMemcpyHostToDevice), EMOGI_E_HIP);
     return EMOGI_OK;
 }
 
@@ -549,16 +588,17 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
         return EMOGI_E_HIP;
     }
     if (flags & EMOGI_F_PACK)
-        st = pack_lists(g, row_ptr, col);  // g->col stays null: the scans decode the packed lists
+        // g->col and g->weights stay null: the scans decode the packed streams
+        st = pack_lists(g, row_ptr, col, weights);
     else
         st = place(g, col, E * col_bytes, &g->col, &g->col_kind);
-    if (st == EMOGI_OK && weights) {
+    if (st == EMOGI_OK && weights && !(flags & EMOGI_F_PACK)) {
         void *w = nullptr;
         st = place(g, weights, E * sizeof(uint32_t), &w, &g->w_kind);
         g->weights = static_cast<uint32_t *>(w);
         // the per-target bound pays only where a weight read crosses the
         // host link; from HBM the extra gather costs more than it saves
-        if (st == EMOGI_OK && E > 0 && placement == EMOGI_PLACE_HOST_ZERO_COPY) st = compute_in_min(g, col);
+        if (st == EMOGI_OK && E > 0 && placement == EMOGI_PLACE_HOST_ZERO_COPY) st = compute_in_min(g);
     }
     if (st == EMOGI_OK) {
         for (hipEvent_t *e : {&g->ev_begin, &g->ev_end, &g->ev_k0, &g->ev_k1})
@@ -577,12 +617,13 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
     return EMOGI_OK;
 }
 
-emogi_status_t emogi_packed_bytes(emogi_graph_t g, uint64_t *bytes) {
-    if (!g || !bytes) {
+emogi_status_t emogi_packed_bytes(emogi_graph_t g, uint64_t *id_bytes, uint64_t *weight_bytes) {
+    if (!g || !id_bytes) {
         set_error("null argument");
         return EMOGI_E_INVALID;
     }
-    *bytes = g->packed.words * 4;
+    *id_bytes = g->packed.words * 4;
+    if (weight_bytes) *weight_bytes = g->packed.wwords * 4;
     return EMOGI_OK;
 }
 

@@ -64,6 +64,14 @@ struct Packed {
     uint64_t *off = nullptr;     // HBM, V + 1 word offsets
     uint8_t *width = nullptr;    // HBM, V gap widths in bits (0..32)
     uint64_t words = 0;          // stream length
+    // Weights (when given) are packed per list too, in a stream of their own:
+    // list u's d weights at the list's weight width ww, back to back from
+    // word woff[u], so block k's weights start at word woff[u] + 2 * ww * k.
+    uint32_t *wstream = nullptr;
+    void *wpinned = nullptr;
+    uint64_t *woff = nullptr;    // HBM, V + 1
+    uint8_t *wwidth = nullptr;   // HBM, V weight widths in bits (0..32)
+    uint64_t wwords = 0;
 };
 
 struct Pool {

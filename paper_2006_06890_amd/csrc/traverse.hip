@@ -116,8 +116,9 @@ __device__ __forceinline__ void uf_link(uint32_t *parent, uint32_t a, uint32_t b
 // for a later band, else 0; SSSP adds kWeightRead when it read the weight.
 constexpr int kWeightRead = 4;
 
-template <int A>
-__device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v, const uint32_t *wp) {
+template <int A, bool kGivenWeight = false>
+__device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v, const uint32_t *wp,
+                                     uint32_t wv = 0) {
     if (v >= a.V) return 0;
     if (A == A_BFS) {
         // BFS: an unvisited neighbour is visited at the next level.
@@ -133,20 +134,28 @@ __device__ __forceinline__ int visit(const OpArgs &a, uint32_t uval, uint32_t v,
         // weight is read (over the host link) only when the edge can improve
         // v: with dist(v) <= dist(u) + the smallest weight of an edge into v
         // it cannot.  Both bounds are HBM reads issued together.
+        // (kGivenWeight: the weight wv came in a packed block with the id.)
         const uint32_t cur = a.state[v];
-        const uint32_t lo = a.inmin ? max(a.wmin, uint32_t(a.inmin[v])) : a.wmin;
-        const uint64_t floor_nd = uint64_t(uval) + lo;
-        if (floor_nd <= 0xFFFFFFFEull && cur <= floor_nd) return 0;
-        const uint64_t nd = uint64_t(uval) + *wp;
+        uint64_t nd;
+        int flag = 0;
+        if constexpr (!kGivenWeight) {
+            const uint32_t lo = a.inmin ? max(a.wmin, uint32_t(a.inmin[v])) : a.wmin;
+            const uint64_t floor_nd = uint64_t(uval) + lo;
+            if (floor_nd <= 0xFFFFFFFEull && cur <= floor_nd) return 0;
+            nd = uint64_t(uval) + *wp;
+            flag = kWeightRead;
+        } else {
+            nd = uint64_t(uval) + wv;
+        }
         if (nd > 0xFFFFFFFEull) {
             atomicOr(&a.bitmap[v >> 5], 1u << (v & 31u));
             atomicOr(&a.ctr[C_OVERFLOW], 1ull);
-            return kWeightRead;
+            return flag;
         }
-        if (cur <= uint32_t(nd)) return kWeightRead;
+        if (cur <= uint32_t(nd)) return flag;
         uint32_t old = atomicMin(&a.state[v], uint32_t(nd));
-        if (old <= uint32_t(nd)) return kWeightRead;
-        return kWeightRead | (uint32_t(nd) < a.split ? 1 : 2);
+        if (old <= uint32_t(nd)) return flag;
+        return flag | (uint32_t(nd) < a.split ? 1 : 2);
     } else if (A == A_LINK) {
         uf_link(a.state, uval, v);
         return 0;
@@ -191,6 +200,9 @@ struct ScanArgs {
     const uint32_t *pk = nullptr;        // packed lists (EMOGI_F_PACK; col is then unused)
     const uint64_t *pk_off = nullptr;    // word offset of each packed list (V + 1)
     const uint8_t *pk_width = nullptr;   // gap width of each packed list, bits
+    const uint32_t *pkw = nullptr;       // packed weights (null: none)
+    const uint64_t *pkw_off = nullptr;   // word offset of each list's weights (V + 1)
+    const uint8_t *pkw_width = nullptr;  // weight width of each list, bits
 };
 
 // Tag for packed lists in the ColT slot of the V5 and PageRank kernels.
@@ -417,6 +429,8 @@ struct ChunkCursor {
     ListSrc<ColT> src;
     uint64_t pw0, pw1;       // packed: the list's words [pw0, pw1)
     uint32_t pwidth, pfull;  // packed: gap width, words per full block
+    uint64_t wo0, wo1;       // packed SSSP: the list's weight words [wo0, wo1)
+    uint32_t wwidth;         // packed SSSP: weight width
 };
 
 // kUnroll chunks' neighbours (and weights), loaded, not yet visited.
@@ -428,9 +442,11 @@ struct ChunkGroup {
     uint32_t uv[kUnroll];
     uint64_t wbase[kUnroll];
     bool tier[kUnroll];
-    // packed lists: the word after v[i] (when the gap straddles it), the bit
-    // shift and the gap width, decoded once the loads are back
-    uint32_t hi[kUnroll], sh[kUnroll], pw[kUnroll];
+    // packed lists: the word after v[i] (when the gap straddles it), then the
+    // bit shifts and widths of the gap (bits 0-15) and of the weight (16-31),
+    // decoded once the loads are back; SSSP: the weight's words likewise
+    uint32_t hi[kUnroll], shw[kUnroll];
+    uint32_t wv[kUnroll], whi[kUnroll];
 };
 
 template <class ColT, int A>
@@ -445,6 +461,11 @@ __device__ __forceinline__ void enter_entry(ChunkCursor<ColT> &c, const ScanArgs
         c.pw1 = uniform64(s.pk_off[c.u + 1]);
         c.pwidth = uniform32(s.pk_width[c.u]);
         c.pfull = packed_block_words(c.pwidth);
+        if (A == A_SSSP) {
+            c.wo0 = uniform64(s.pkw_off[c.u]);
+            c.wo1 = uniform64(s.pkw_off[c.u + 1]);
+            c.wwidth = uniform32(s.pkw_width[c.u]);
+        }
     }
 }
 
@@ -476,9 +497,12 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
         g.wbase[i] = 0;
         g.tier[i] = false;
         g.uv[i] = c.uval;
-        g.hi[i] = 0;
-        g.sh[i] = 0;
-        g.pw[i] = 0;
+        if constexpr (kPacked<ColT>) {
+            g.hi[i] = 0;
+            g.shw[i] = 0;
+            g.wv[i] = 0;
+            g.whi[i] = 0;
+        }
         if (kk < c.kend) {
             while (kk >= c.qnext) {  // next entry that owns chunks (uniform)
                 ++c.q;
@@ -488,9 +512,13 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
             }
             g.uv[i] = c.uval;
             if (kk == c.qfirst && lane == 0) {
-                if constexpr (kPacked<ColT>)
+                if constexpr (kPacked<ColT>) {
                     count_packed(c.b, c.e, c.pw0, c.pw1, s.req_unit, edges, reqb, verts, pkb);
-                else
+                    if (A == A_SSSP) {
+                        reqb += request_bytes(c.wo0, c.wo1, 4, s.req_unit);
+                        pkb += (c.wo1 - c.wo0) * 4;
+                    }
+                } else
                     count_list(c.src.tier, c.b, c.e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
             }
             const uint64_t j0 = uniform64((c.b & ~s.align_mask) + (kk - c.qfirst) * kWave);
@@ -504,18 +532,31 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
                 // lane l the gap to id l, bits [(l-1)w, lw) after that word
                 const uint64_t wb = c.pw0 + (kk - c.qfirst) * c.pfull;
                 const uint32_t w = c.pwidth;
-                g.pw[i] = w;
+                uint32_t sh = 0;
                 if (g.ok[i]) {
                     if (lane == 0) {
                         g.v[i] = s.pk[wb];
                     } else if (w) {
                         const uint64_t o = uint64_t(lane - 1) * w;
                         const uint64_t wd = wb + 1 + (o >> 5);
-                        g.sh[i] = uint32_t(o & 31u);
+                        sh = uint32_t(o & 31u);
                         g.v[i] = s.pk[wd];
-                        if (g.sh[i] + w > 32u) g.hi[i] = s.pk[wd + 1];
+                        if (sh + w > 32u) g.hi[i] = s.pk[wd + 1];
                     }
                 }
+                uint32_t wsh = 0, ww = 0;
+                if (A == A_SSSP) {
+                    // weight j of the list: bits [j ww, (j+1) ww) of its weight words
+                    ww = c.wwidth;
+                    if (g.ok[i] && ww) {
+                        const uint64_t o = (j - c.b) * ww;
+                        const uint64_t wd = c.wo0 + (o >> 5);
+                        wsh = uint32_t(o & 31u);
+                        g.wv[i] = s.pkw[wd];
+                        if (wsh + ww > 32u) g.whi[i] = s.pkw[wd + 1];
+                    }
+                }
+                g.shw[i] = sh | (w << 8) | (wsh << 16) | (ww << 24);
             } else {
                 if (g.ok[i]) g.v[i] = load_col(c.src.col, j - c.src.shift);
             }
@@ -524,12 +565,18 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
     if constexpr (kPacked<ColT>) {
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i) {
+            const uint32_t sh = g.shw[i] & 0xFFu, w = (g.shw[i] >> 8) & 0xFFu;
             uint32_t x = g.v[i];
             if (lane != 0) {
                 const uint64_t word = (uint64_t(g.hi[i]) << 32) | g.v[i];
-                x = uint32_t((word >> g.sh[i]) & ((uint64_t(1) << g.pw[i]) - 1));
+                x = uint32_t((word >> sh) & ((uint64_t(1) << w) - 1));
             }
             g.v[i] = wave_prefix_sum(x, lane);  // first id + the gaps up to each lane
+            if (A == A_SSSP) {
+                const uint32_t wsh = (g.shw[i] >> 16) & 0xFFu, ww = g.shw[i] >> 24;
+                const uint64_t word = (uint64_t(g.whi[i]) << 32) | g.wv[i];
+                g.wv[i] = uint32_t((word >> wsh) & ((uint64_t(1) << ww) - 1));
+            }
         }
     }
     c.kb += kUnroll;
@@ -540,10 +587,9 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
 // the next group's loads in flight during the visits measured no faster:
 // vector loads return in issue order, so the visits' HBM loads wait for them.)
 template <class ColT, int A>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_balanced(ScanArgs s0,
-                                                                                           OpArgs a) {
+__device__ __forceinline__ void balanced_body(const ScanArgs &s0, const OpArgs &a,
+                                              uint32_t (*seg)[kSegCap]) {
     const ScanArgs s = resolved(s0);
-    __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
     uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0, pkb = 0;
@@ -556,12 +602,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
         load_group<ColT, A>(c, g, s, a, lane, edges, reqb, verts, tedges, pkb);
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i) {
-            const int r = g.ok[i] ? visit<A>(a, g.uv[i], g.v[i], reinterpret_cast<const uint32_t *>(g.wbase[i]) + lane) : 0;
+            int r = 0;
+            if (g.ok[i]) {
+                if constexpr (kPacked<ColT>)
+                    r = visit<A, true>(a, g.uv[i], g.v[i], nullptr, g.wv[i]);
+                else
+                    r = visit<A>(a, g.uv[i], g.v[i], reinterpret_cast<const uint32_t *>(g.wbase[i]) + lane);
+            }
             if ((r & kWeightRead) && !g.tier[i]) ++wlink;
             emit<A>(st, r & 3, g.v[i], s.next, a, lane);
         }
     }
     finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink, pkb);
+}
+
+template <class ColT, int A>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_balanced(ScanArgs s0,
+                                                                                           OpArgs a) {
+    __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
+    balanced_body<ColT, A>(s0, a, seg);
+}
+
+// V5 over packed lists; the decoding needs more registers than the 6 waves
+// per SIMD of the plain kernel allow without spilling.
+template <int A>
+__global__ __launch_bounds__(kBlock) void k_balanced_packed(ScanArgs s0, OpArgs a) {
+    __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
+    balanced_body<PackedCol, A>(s0, a, seg);
 }
 
 // ---------------------------------------------------------------------------
@@ -1039,7 +1106,7 @@ static void launch_variant(int var, const ScanArgs &s, const OpArgs &a, hipStrea
 // Packed lists are scanned by V5 only (their chunks are their blocks).
 template <int A>
 static void launch_packed(const ScanArgs &s, const OpArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL((k_balanced<PackedCol, A>), dim3(kMaxGrid), dim3(kBlock), 0, stream, s, a);
+    hipLaunchKernelGGL((k_balanced_packed<A>), dim3(kMaxGrid), dim3(kBlock), 0, stream, s, a);
 }
 
 // Points a scan at the graph's packed lists (no-op for plain lists).
@@ -1048,6 +1115,9 @@ static void use_packed(ScanArgs &s, const emogi_graph_s *g) {
     s.pk = g->packed.stream;
     s.pk_off = g->packed.off;
     s.pk_width = g->packed.width;
+    s.pkw = g->packed.wstream;
+    s.pkw_off = g->packed.woff;
+    s.pkw_width = g->packed.wwidth;
     s.align_mask = 0;
 }
 
@@ -1141,7 +1211,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                   (unsigned long long)g->V);
         return EMOGI_E_INVALID;
     }
-    if (algo == A_SSSP && !g->weights) {
+    if (algo == A_SSSP && !g->weights && !g->packed.wstream) {
         set_error("SSSP needs edge weights");
         return EMOGI_E_INVALID;
     }

@@ -188,7 +188,7 @@ def lib():
             "emogi_host_free": (i32, [p]),
             "emogi_graph_create": (i32, [p, u64, p, u32, p, i32, u32, ctypes.POINTER(ctypes.c_void_p)]),
             "emogi_graph_destroy": (i32, [p]),
-            "emogi_packed_bytes": (i32, [p, ctypes.POINTER(ctypes.c_uint64)]),
+            "emogi_packed_bytes": (i32, [p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
             "emogi_set_request_unit": (i32, [p, u32]),
             "emogi_set_scheduler": (i32, [p, i32]),
             "emogi_set_sssp_delta": (i32, [p, u32]),
@@ -321,10 +321,10 @@ class Graph:
             self._keep = None  # copied by the library
 
     def packed_bytes(self):
-        """Bytes of the packed lists (0 unless created with ``pack``)."""
-        b = ctypes.c_uint64()
-        check(lib().emogi_packed_bytes(self._h, ctypes.byref(b)))
-        return b.value
+        """(id bytes, weight bytes) of the packed lists (zeros unless created with ``pack``)."""
+        b, wb = ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib().emogi_packed_bytes(self._h, ctypes.byref(b), ctypes.byref(wb)))
+        return b.value, wb.value
 
     # -- configuration -------------------------------------------------------
     def set_variant(self, v):

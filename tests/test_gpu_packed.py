@@ -56,6 +56,18 @@ def _packed_words(rp, col):
     return words
 
 
+def _packed_weight_words(rp, w):
+    """Words of each list's weights: all of them at the list's width (the
+    bit length of its largest weight), back to back."""
+    V = rp.shape[0] - 1
+    words = np.zeros(V, dtype=np.int64)
+    for u in range(V):
+        ws = [int(x) for x in w[int(rp[u]):int(rp[u + 1])]]
+        ww = max(ws, default=0).bit_length()
+        words[u] = (len(ws) * ww + 31) // 32
+    return words
+
+
 def _sources(g):
     deg = g.degrees()
     nz = np.flatnonzero(deg > 0)
@@ -75,7 +87,8 @@ def test_packed_traversals_match_oracle(gpu_device, name, col_bytes, placement):
     col = g.col.astype(np.uint32 if col_bytes == 4 else np.uint64)
     out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
     with E.Graph(g.row_ptr, col, g.weights, placement=placement, symmetric=SYMMETRIC[name], pack=True) as G:
-        assert G.packed_bytes() == 4 * int(_packed_words(g.row_ptr, g.col).sum())
+        assert G.packed_bytes() == (4 * int(_packed_words(g.row_ptr, g.col).sum()),
+                                    4 * int(_packed_weight_words(g.row_ptr, g.weights).sum()))
         for s in _sources(g):
             for ordered in (True, False):
                 G.set_frontier_order(ordered)
@@ -87,6 +100,9 @@ def test_packed_traversals_match_oracle(gpu_device, name, col_bytes, placement):
                 G.sssp(s, out)
                 np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(g.row_ptr, g.col, g.weights, s),
                                               err_msg=f"sssp {name} s{s} delta {delta}")
+                st = G.stats()
+                assert st["weights_read"] == 0
+                assert st["useful_link_bytes"] <= st["request_bytes"]
         if SYMMETRIC[name]:
             exp = oracle.cc(g.row_ptr, g.col)
             for algo in ("sampled_union_find", "label_propagation"):
@@ -117,7 +133,9 @@ def test_packed_link_bytes(gpu_device):
         assert st["edges_scanned"] == int(g.degrees()[reached].sum())
         assert st["useful_link_bytes"] == 4 * int(words[reached].sum())
         assert st["request_bytes"] >= st["useful_link_bytes"]
-        assert G.packed_bytes() < 0.75 * 4 * g.num_edges
+        assert G.packed_bytes()[0] < 0.6 * 4 * g.num_edges      # ids: well under 4 bytes
+        # weights 1..255: at most 8 bits each, each list rounded up to a word
+        assert G.packed_bytes()[1] <= g.num_edges + 3 * int((g.degrees() > 0).sum())
         assert set(st["level_variant"]) == {5}
 
 
@@ -142,7 +160,7 @@ def test_packed_wide_gaps(gpu_device):
         words = np.zeros(V, dtype=np.int64)
         words[nz] = _packed_words(np.concatenate([[0], np.cumsum(g.degrees()[nz])]).astype(np.uint64),
                                   g.col)
-        assert G.packed_bytes() == 4 * int(words.sum())
+        assert G.packed_bytes()[0] == 4 * int(words.sum())
         for s in (0, int(nz[len(nz) // 2]), V - 1, 3):
             G.bfs(s, out)
             np.testing.assert_array_equal(E.to_u32(out), oracle.bfs(g.row_ptr, g.col, s), err_msg=f"bfs s{s}")
@@ -167,3 +185,40 @@ def test_packed_rejects(gpu_device):
             with pytest.raises(E.EmogiError) as ex:
                 call()
             assert ex.value.code == -8
+
+
+def test_packed_weight_widths_and_overflow(gpu_device):
+    """Weights of 32 bits (width 32), of 0 (width 0) and mixed widths; an
+    overflowing path is reported as on plain lists (-6), a merely long one
+    gives the exact distances."""
+    import torch
+    import paper_2006_06890_amd as E
+    big = 0x80000000
+    g = graphgen.from_edges(3, [(0, 1), (1, 2)], weights=[big, big])
+    out = torch.empty(3, dtype=torch.int32, device="cuda")
+    with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True, pack=True) as G:
+        with pytest.raises(E.EmogiError) as ei:
+            G.sssp(0, out)
+        assert ei.value.code == -6
+    g2 = graphgen.from_edges(4, [(0, 1), (1, 2), (0, 3), (3, 2)], weights=[big, big, 5, 7])
+    out = torch.empty(4, dtype=torch.int32, device="cuda")
+    with E.Graph(g2.row_ptr, g2.col, g2.weights, symmetric=True, pack=True) as G:
+        G.sssp(0, out)
+        np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(g2.row_ptr, g2.col, g2.weights, 0))
+    rng = np.random.Generator(np.random.PCG64(21))
+    h = graphgen.rmat(11, seed=4).to_csr(4)
+    for kind in ("zero", "wide", "mixed"):
+        if kind == "zero":
+            w = np.zeros(h.num_edges, dtype=np.uint32)
+        elif kind == "wide":
+            w = rng.integers(1 << 31, (1 << 32) - 1, size=h.num_edges, dtype=np.uint64).astype(np.uint32) >> 10
+        else:
+            w = (rng.integers(0, 1 << 32, size=h.num_edges, dtype=np.uint64) >> rng.integers(0, 32, size=h.num_edges,
+                                                                                      dtype=np.uint64)).astype(np.uint32) >> 8
+        out = torch.empty(h.num_vertices, dtype=torch.int32, device="cuda")
+        with E.Graph(h.row_ptr, h.col, w, pack=True) as G:
+            assert G.packed_bytes()[1] == 4 * int(_packed_weight_words(h.row_ptr, w).sum())
+            for s in _sources(h):
+                G.sssp(s, out)
+                np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(h.row_ptr, h.col, w, s),
+                                              err_msg=f"{kind} s{s}")
