@@ -58,6 +58,9 @@ def workload_name(args):
     kind = "Kronecker/R-MAT" if args.workload == "kron" else "uniform random"
     size = f"scale {args.scale}, edgefactor 16" if args.workload == "kron" else \
         f"2^{args.scale} vertices, 2^{args.scale} x 32 samples"
+    if args.pack:
+        return (f"{kind} {size}, packed lists (from u{8 * args.col_bytes} ids + u32 weights; ids and weights "
+                f"bit-packed per list) in pinned host zero-copy memory")
     return f"{kind} {size}, u{8 * args.col_bytes} col + u32 weights in pinned host zero-copy memory"
 
 
@@ -92,10 +95,12 @@ def run_step(G, src, out, algos=("bfs", "sssp", "cc")):
     return res
 
 
-def kernel_key(algo, variant, col_bytes):
+def kernel_key(algo, variant, col_bytes, packed=False):
     """The scan kernel's template name as the profiler prints it."""
     t = "unsigned long" if col_bytes == 8 else "unsigned int"
     a = {"bfs": 0, "sssp": 1, "cc": 2}[algo]
+    if packed:
+        return f"k_balanced_packed<{a}>"
     names = [f"k_group<{t}, {a}, 1>", f"k_group<{t}, {a}, 16>", f"k_wave<{t}, {a}, false>",
              f"k_wave<{t}, {a}, true>", f"k_block<{t}, {a}>", f"k_balanced<{t}, {a}>"]
     return names[variant]
@@ -106,7 +111,8 @@ KERNEL_SOURCES = ["paper_2006_06890_amd/csrc/traverse.hip", "paper_2006_06890_am
 
 
 def counters_path(args):
-    return os.path.join(ROOT, "profiles", f"counters_{args.config}_u{8 * args.col_bytes}.json")
+    tag = "_packed" if args.pack else ""
+    return os.path.join(ROOT, "profiles", f"counters_{args.config}_u{8 * args.col_bytes}{tag}.json")
 
 
 def kernel_sources_sha1():
@@ -190,6 +196,9 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-source batched runs")
     ap.add_argument("--noncoherent", action="store_true", help="pin the edge arrays non-coherent")
+    ap.add_argument("--pack", action="store_true",
+                    help="measure the packed lists (EMOGI_F_PACK) instead of the plain arrays; "
+                         "no batched runs, tier or packed arms")
     ap.add_argument("--no-learned", action="store_true", help="skip the scheduler comparison")
     ap.add_argument("--no-autotune", action="store_true", help="batched26: keep the default batch parameters")
     ap.add_argument("--pagerank-iters", type=int, default=3,
@@ -201,6 +210,11 @@ def parse_args():
     ap.add_argument("--calibrate-only", action="store_true",
                     help="run the link calibration (plain zero-copy read kernels) and exit")
     args = ap.parse_args()
+    if args.pack:
+        if args.config == "batched26":
+            sys.exit("--pack: batched traversal reads plain lists")
+        args.no_batch = True
+        args.tier_fracs = ""
     preset = PRESETS[args.config]
     args.workload = preset["workload"]
     args.algos = preset["algos"]
@@ -227,7 +241,7 @@ def base_result(args, value, elapsed, V, M, profile):
         "config": {
             "workload": workload_name(args) + "; " + "+".join(a.upper() for a in args.algos) + " per step",
             "preset": args.config, "vertices": V, "directed_edges": M, "col_bytes": args.col_bytes,
-            "placement": "host_zero_copy", "request_unit": args.request_unit,
+            "placement": "host_zero_copy", "request_unit": args.request_unit, "packed": bool(args.pack),
         },
         "host_link": {
             "pinned_memcpy_peak_GBps": round(profile["memcpy_GBps"], 2),
@@ -301,7 +315,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             # where the edge can improve its target), spread over its levels
             eb = st["useful_link_bytes"] / max(1, st["edges_scanned"])
             for v, ms, ed in zip(st["level_variant"], st["level_ms"], st["level_edges"]):
-                k = kernel_key(a, v, args.col_bytes)
+                k = kernel_key(a, v, args.col_bytes, args.pack)
                 kk = kernels.setdefault(k, {"ms": 0.0, "bytes": 0, "launches": 0})
                 kk["ms"] += ms
                 kk["bytes"] += ed * eb
@@ -415,7 +429,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             }
             H.close()
             log(f"[bench] arm {placement}: {arms[placement]}")
-    if not args.no_arms:
+    if not args.no_arms and not args.pack:
         # packed lists (the compression Sec. 6 proposes): the same graph with
         # ids and weights bit-packed per list, every source of the step
         t0 = time.perf_counter()
@@ -550,7 +564,7 @@ def main():
     rp, col, w = build_graph(args, E, graphgen)
     V = rp.shape[0] - 1
     deg = np.diff(rp)
-    G = E.Graph(rp, col, w, placement="host_zero_copy", symmetric=True, borrow=True)
+    G = E.Graph(rp, col, w, placement="host_zero_copy", symmetric=True, borrow=True, pack=args.pack)
     G.set_request_unit(args.request_unit)
     if args.scheduler.isdigit():
         G.set_variant(int(args.scheduler))

@@ -165,9 +165,9 @@ emogi_status_t emogi_host_free(void *p);
  * decoding on the GPU that Sec. 6 proposes to cut link traffic: each list
  * (ascending ids required, else EMOGI_E_INVALID) is cut into blocks of 64
  * ids, a block being its first id as a 32-bit word and then the gaps to the
- * next ids bit-packed at the list's gap width; a list's weights are
+ * next ids bit-packed at the list's gap width, then the block's weights
  * bit-packed at the list's weight width (the bit length of its largest
- * weight) in a second stream.  Both go where the placement puts the lists;
+ * weight).  The blocks go where the placement puts the lists;
  * col and weights are read only during creation.  BFS, SSSP, CC and
  * PageRank scan packed lists with the edge-balanced variant (V5) whatever
  * the scheduler; SSSP then reads each scanned list's packed weights whole.

@@ -120,13 +120,8 @@ static void release(emogi_graph_s *g) {
     free_edges(g->weights, g->w_kind);
     if (g->row_ptr) (void)hipFree(g->row_ptr);
     if (g->in_min) (void)hipFree(g->in_min);
-    if (g->packed.on_device) {
-        if (g->packed.stream) (void)hipFree(g->packed.stream);
-        if (g->packed.wstream) (void)hipFree(g->packed.wstream);
-    }
+    if (g->packed.on_device && g->packed.stream) (void)hipFree(g->packed.stream);
     if (g->packed.pinned) (void)hipHostFree(g->packed.pinned);
-    if (g->packed.wpinned) (void)hipHostFree(g->packed.wpinned);
-    if (g->packed.woff) (void)hipFree(g->packed.woff);
     if (g->packed.wwidth) (void)hipFree(g->packed.wwidth);
     if (g->packed.off) (void)hipFree(g->packed.off);
     if (g->packed.width) (void)hipFree(g->packed.width);
@@ -290,9 +285,14 @@ struct BitWriter {
     }
 };
 
+// Words of one packed block of `cnt` ids (gap width w, weight width ww).
+static inline uint64_t block_words(uint64_t cnt, uint32_t w, uint32_t ww) {
+    return 1 + ((cnt - 1) * w + 31) / 32 + (cnt * ww + 31) / 32;
+}
+
 // EMOGI_F_PACK: encodes the lists (and weights) on the host threads in two
 // passes over col: widths and word counts, then the blocks, straight into
-// the streams' final host memory (pinned) or host buffers copied to HBM.
+// the stream's final host memory (pinned) or a host buffer copied to HBM.
 static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, const void *col,
                                  const uint32_t *weights) {
     const uint64_t V = g->V;
@@ -302,7 +302,7 @@ static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, cons
         return EMOGI_E_UNSUPPORTED;
     }
     std::vector<uint8_t> width(V), wwidth(weights ? V : 0);
-    std::vector<uint64_t> off(V + 1, 0), woff(weights ? V + 1 : 0, 0);
+    std::vector<uint64_t> off(V + 1, 0), wcount(V, 0);
     std::atomic<uint64_t> bad{~uint64_t(0)};
     parallel_for(V, [&](uint64_t u0, uint64_t u1) {
         for (uint64_t u = u0; u < u1; ++u) {
@@ -321,16 +321,14 @@ static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, cons
                 if (weights) maxw = std::max(maxw, weights[i]);
             }
             const uint32_t w = maxgap ? 64u - uint32_t(__builtin_clzll(maxgap)) : 0u;
+            const uint32_t ww = maxw ? 32u - uint32_t(__builtin_clz(maxw)) : 0u;
             width[u] = uint8_t(w);
+            if (weights) wwidth[u] = uint8_t(ww);
             const uint64_t d = e - b;
             if (d) {
                 const uint64_t nb = (d + 63) / 64, last = d - (nb - 1) * 64;
-                off[u + 1] = (nb - 1) * (1 + (63 * uint64_t(w) + 31) / 32) + 1 + ((last - 1) * w + 31) / 32;
-            }
-            if (weights) {
-                const uint32_t ww = maxw ? 32u - uint32_t(__builtin_clz(maxw)) : 0u;
-                wwidth[u] = uint8_t(ww);
-                woff[u + 1] = (d * ww + 31) / 32;
+                off[u + 1] = (nb - 1) * block_words(64, w, ww) + block_words(last, w, ww);
+                wcount[u] = (nb - 1) * 2 * uint64_t(ww) + (last * ww + 31) / 32;
             }
         }
     });
@@ -339,21 +337,22 @@ static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, cons
                   (unsigned long long)bad.load());
         return EMOGI_E_INVALID;
     }
-    for (uint64_t u = 0; u < V; ++u) off[u + 1] += off[u];
-    if (weights)
-        for (uint64_t u = 0; u < V; ++u) woff[u + 1] += woff[u];
+    uint64_t wwords = 0;
+    for (uint64_t u = 0; u < V; ++u) {
+        off[u + 1] += off[u];
+        wwords += wcount[u];
+    }
     Packed &pk = g->packed;
-    const uint64_t words = off[V], wwords = weights ? woff[V] : 0;
-    const size_t bytes = std::max<size_t>(8, words * 4), wbytes = std::max<size_t>(8, wwords * 4);
-    uint32_t *host = nullptr, *whost = nullptr;
-    std::vector<uint32_t> staging, wstaging;
+    const uint64_t words = off[V];
+    const size_t bytes = std::max<size_t>(8, words * 4);
+    uint32_t *host = nullptr;
+    std::vector<uint32_t> staging;
     emogi_status_t st = alloc_stream(g, bytes, &pk.pinned, &host, staging);
-    if (st == EMOGI_OK && weights) st = alloc_stream(g, wbytes, &pk.wpinned, &whost, wstaging);
     if (st != EMOGI_OK) return st;
     parallel_for(V, [&](uint64_t u0, uint64_t u1) {
         for (uint64_t u = u0; u < u1; ++u) {
             const uint64_t b = row_ptr[u], e = row_ptr[u + 1];
-            const uint32_t w = width[u];
+            const uint32_t w = width[u], ww = weights ? wwidth[u] : 0u;
             BitWriter bw{host + off[u]};
             for (uint64_t k0 = b; k0 < e; k0 += 64) {
                 const uint64_t k1 = std::min(e, k0 + 64);
@@ -365,11 +364,10 @@ static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, cons
                     prev = x;
                 }
                 bw.flush();
-            }
-            if (weights) {
-                BitWriter ws{whost + woff[u]};
-                for (uint64_t i = b; i < e; ++i) ws.put(weights[i], wwidth[u]);
-                ws.flush();
+                if (ww) {
+                    for (uint64_t i = k0; i < k1; ++i) bw.put(weights[i], ww);
+                    bw.flush();
+                }
             }
         }
     });
@@ -377,7 +375,6 @@ static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, cons
     pk.wwords = wwords;
     if ((st = publish_stream(g, bytes, pk.pinned, host, &pk.stream)) != EMOGI_OK) return st;
     if (g->placement != EMOGI_PLACE_HOST_ZERO_COPY) pk.on_device = true;
-    if (weights && (st = publish_stream(g, wbytes, pk.wpinned, whost, &pk.wstream)) != EMOGI_OK) return st;
     auto upload = [&](void **dst, const void *src, size_t n) -> emogi_status_t {
         if (hipMalloc(dst, std::max<size_t>(n, 8)) != hipSuccess) {
             (void)hipGetLastError();
@@ -390,10 +387,7 @@ static emogi_status_t pack_lists(emogi_graph_s *g, const uint64_t *row_ptr, cons
     };
     if ((st = upload(reinterpret_cast<void **>(&pk.off), off.data(), (V + 1) * 8)) != EMOGI_OK) return st;
     if ((st = upload(reinterpret_cast<void **>(&pk.width), width.data(), V)) != EMOGI_OK) return st;
-    if (weights) {
-        if ((st = upload(reinterpret_cast<void **>(&pk.woff), woff.data(), (V + 1) * 8)) != EMOGI_OK) return st;
-        if ((st = upload(reinterpret_cast<void **>(&pk.wwidth), wwidth.data(), V)) != EMOGI_OK) return st;
-    }
+    if (weights && (st = upload(reinterpret_cast<void **>(&pk.wwidth), wwidth.data(), V)) != EMOGI_OK) return st;
     return EMOGI_OK;
 }
 
@@ -622,7 +616,7 @@ emogi_status_t emogi_packed_bytes(emogi_graph_t g, uint64_t *id_bytes, uint64_t 
         set_error("null argument");
         return EMOGI_E_INVALID;
     }
-    *id_bytes = g->packed.words * 4;
+    *id_bytes = (g->packed.words - g->packed.wwords) * 4;
     if (weight_bytes) *weight_bytes = g->packed.wwords * 4;
     return EMOGI_OK;
 }

@@ -54,24 +54,19 @@ struct Tier {
 
 // Packed neighbour lists (EMOGI_F_PACK).  Each list is cut into blocks of
 // 64 ids; a block is its first id as a whole word, then the gaps to the next
-// ids (at most 63) at the list's gap width, bit-packed into words.  Every
-// block but a list's last is full, so block k of list u starts at word
-// off[u] + k * (1 + ceil(63 * width[u] / 32)).
+// ids (at most 63) at the list's gap width w, then (with weights) the
+// block's weights at the list's weight width ww, each part bit-packed into
+// whole words.  Every block but a list's last is full, so block k of list u
+// starts at word off[u] + k * (1 + ceil(63 w / 32) + 2 ww).
 struct Packed {
     uint32_t *stream = nullptr;  // the blocks of all lists, as the GPU addresses them
     void *pinned = nullptr;      // host allocation behind stream (zero-copy placement)
     bool on_device = false;      // stream is in HBM
     uint64_t *off = nullptr;     // HBM, V + 1 word offsets
     uint8_t *width = nullptr;    // HBM, V gap widths in bits (0..32)
+    uint8_t *wwidth = nullptr;   // HBM, V weight widths in bits (0..32), or null: no weights
     uint64_t words = 0;          // stream length
-    // Weights (when given) are packed per list too, in a stream of their own:
-    // list u's d weights at the list's weight width ww, back to back from
-    // word woff[u], so block k's weights start at word woff[u] + 2 * ww * k.
-    uint32_t *wstream = nullptr;
-    void *wpinned = nullptr;
-    uint64_t *woff = nullptr;    // HBM, V + 1
-    uint8_t *wwidth = nullptr;   // HBM, V weight widths in bits (0..32)
-    uint64_t wwords = 0;
+    uint64_t wwords = 0;         // of which weight words
 };
 
 struct Pool {

@@ -200,9 +200,7 @@ struct ScanArgs {
     const uint32_t *pk = nullptr;        // packed lists (EMOGI_F_PACK; col is then unused)
     const uint64_t *pk_off = nullptr;    // word offset of each packed list (V + 1)
     const uint8_t *pk_width = nullptr;   // gap width of each packed list, bits
-    const uint32_t *pkw = nullptr;       // packed weights (null: none)
-    const uint64_t *pkw_off = nullptr;   // word offset of each list's weights (V + 1)
-    const uint8_t *pkw_width = nullptr;  // weight width of each list, bits
+    const uint8_t *pk_wwidth = nullptr;  // weight width of each packed list, bits (null: no weights)
 };
 
 // Tag for packed lists in the ColT slot of the V5 and PageRank kernels.
@@ -212,8 +210,10 @@ struct PackedCol {
 template <class ColT>
 constexpr bool kPacked = std::is_same<ColT, PackedCol>::value;
 
-// Words of a full packed block (first id + 63 gaps of w bits).
-__device__ __forceinline__ uint32_t packed_block_words(uint32_t w) { return 1u + (63u * w + 31u) / 32u; }
+// Words of a full packed block: first id, 63 gaps of w bits, 64 weights of ww bits.
+__device__ __forceinline__ uint32_t packed_block_words(uint32_t w, uint32_t ww) {
+    return 1u + (63u * w + 31u) / 32u + 2u * ww;
+}
 
 // Inclusive prefix sum over the 64 lanes (every lane calls it).
 __device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t x, int lane) {
@@ -238,14 +238,18 @@ __device__ __forceinline__ void count_list(bool tier, uint64_t b, uint64_t e, ui
     else reqb += request_bytes(b, e, cb, R);
 }
 
-// A packed list counts its edges, its encoded words [w0, w1) as bytes, and
-// those rounded out to the request unit.
-__device__ __forceinline__ void count_packed(uint64_t b, uint64_t e, uint64_t w0, uint64_t w1, uint32_t R,
-                                             uint64_t &edges, uint64_t &reqb, uint64_t &verts, uint64_t &pkb) {
-    edges += e - b;
+// A packed list [b, e) in words [w0, w1) counts its edges, its encoded
+// bytes (without its weight words unless the scan uses the weights), and
+// its words rounded out to the request unit.
+__device__ __forceinline__ void count_packed(uint64_t b, uint64_t e, uint64_t w0, uint64_t w1, uint32_t ww,
+                                             bool weights, uint32_t R, uint64_t &edges, uint64_t &reqb,
+                                             uint64_t &verts, uint64_t &pkb) {
+    const uint64_t d = e - b, nb = (d + 63) / 64, last = d - (nb - 1) * 64;
+    const uint64_t wwords = (nb - 1) * 2 * uint64_t(ww) + (last * ww + 31) / 32;
+    edges += d;
     verts += 1;
     reqb += request_bytes(w0, w1, 4, R);
-    pkb += (w1 - w0) * 4;
+    pkb += (w1 - w0 - (weights ? 0 : wwords)) * 4;
 }
 
 __device__ __forceinline__ uint32_t frontier_at(const ScanArgs &s, uint32_t q) {
@@ -429,8 +433,7 @@ struct ChunkCursor {
     ListSrc<ColT> src;
     uint64_t pw0, pw1;       // packed: the list's words [pw0, pw1)
     uint32_t pwidth, pfull;  // packed: gap width, words per full block
-    uint64_t wo0, wo1;       // packed SSSP: the list's weight words [wo0, wo1)
-    uint32_t wwidth;         // packed SSSP: weight width
+    uint32_t wwidth;         // packed: weight width (0: no weights)
 };
 
 // kUnroll chunks' neighbours (and weights), loaded, not yet visited.
@@ -460,12 +463,8 @@ __device__ __forceinline__ void enter_entry(ChunkCursor<ColT> &c, const ScanArgs
         c.pw0 = uniform64(s.pk_off[c.u]);
         c.pw1 = uniform64(s.pk_off[c.u + 1]);
         c.pwidth = uniform32(s.pk_width[c.u]);
-        c.pfull = packed_block_words(c.pwidth);
-        if (A == A_SSSP) {
-            c.wo0 = uniform64(s.pkw_off[c.u]);
-            c.wo1 = uniform64(s.pkw_off[c.u + 1]);
-            c.wwidth = uniform32(s.pkw_width[c.u]);
-        }
+        c.wwidth = s.pk_wwidth ? uniform32(s.pk_wwidth[c.u]) : 0u;
+        c.pfull = packed_block_words(c.pwidth, c.wwidth);
     }
 }
 
@@ -512,13 +511,10 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
             }
             g.uv[i] = c.uval;
             if (kk == c.qfirst && lane == 0) {
-                if constexpr (kPacked<ColT>) {
-                    count_packed(c.b, c.e, c.pw0, c.pw1, s.req_unit, edges, reqb, verts, pkb);
-                    if (A == A_SSSP) {
-                        reqb += request_bytes(c.wo0, c.wo1, 4, s.req_unit);
-                        pkb += (c.wo1 - c.wo0) * 4;
-                    }
-                } else
+                if constexpr (kPacked<ColT>)
+                    count_packed(c.b, c.e, c.pw0, c.pw1, c.wwidth, A == A_SSSP, s.req_unit, edges, reqb, verts,
+                                 pkb);
+                else
                     count_list(c.src.tier, c.b, c.e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
             }
             const uint64_t j0 = uniform64((c.b & ~s.align_mask) + (kk - c.qfirst) * kWave);
@@ -546,14 +542,17 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
                 }
                 uint32_t wsh = 0, ww = 0;
                 if (A == A_SSSP) {
-                    // weight j of the list: bits [j ww, (j+1) ww) of its weight words
+                    // the block's weights follow its gap words: lane l's at bits
+                    // [l ww, (l+1) ww) of them
                     ww = c.wwidth;
                     if (g.ok[i] && ww) {
-                        const uint64_t o = (j - c.b) * ww;
-                        const uint64_t wd = c.wo0 + (o >> 5);
+                        const uint64_t cnt = c.e - j0 < uint64_t(kWave) ? c.e - j0 : uint64_t(kWave);
+                        const uint64_t wbase = wb + 1 + ((cnt - 1) * w + 31) / 32;
+                        const uint64_t o = uint64_t(lane) * ww;
+                        const uint64_t wd = wbase + (o >> 5);
                         wsh = uint32_t(o & 31u);
-                        g.wv[i] = s.pkw[wd];
-                        if (wsh + ww > 32u) g.whi[i] = s.pkw[wd + 1];
+                        g.wv[i] = s.pk[wd];
+                        if (wsh + ww > 32u) g.whi[i] = s.pk[wd + 1];
                     }
                 }
                 g.shw[i] = sh | (w << 8) | (wsh << 16) | (ww << 24);
@@ -1115,9 +1114,7 @@ static void use_packed(ScanArgs &s, const emogi_graph_s *g) {
     s.pk = g->packed.stream;
     s.pk_off = g->packed.off;
     s.pk_width = g->packed.width;
-    s.pkw = g->packed.wstream;
-    s.pkw_off = g->packed.woff;
-    s.pkw_width = g->packed.wwidth;
+    s.pk_wwidth = g->packed.wwidth;
     s.align_mask = 0;
 }
 
@@ -1211,7 +1208,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                   (unsigned long long)g->V);
         return EMOGI_E_INVALID;
     }
-    if (algo == A_SSSP && !g->weights && !g->packed.wstream) {
+    if (algo == A_SSSP && !g->weights && !g->packed.wwidth) {
         set_error("SSSP needs edge weights");
         return EMOGI_E_INVALID;
     }

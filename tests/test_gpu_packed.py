@@ -1,5 +1,7 @@
 """Packed neighbour lists (EMOGI_F_PACK): the compression with decoding on
-the GPU that Sec. 6 proposes.  Packing changes how the lists travel, never
+the GPU that Sec. 6 proposes.  A list is cut into blocks of 64 ids; a block
+is its first id, the gaps to its other ids at the list's gap width, then
+its weights at the list's weight width, each part in whole 32-bit words.  Packing changes how the lists travel, never
 what a traversal computes, so BFS levels, SSSP distances, CC labels and
 PageRank scores over packed lists must equal the oracle's on the plain lists
 bit for bit; the encoded size is checked against the block format written
@@ -57,14 +59,15 @@ def _packed_words(rp, col):
 
 
 def _packed_weight_words(rp, w):
-    """Words of each list's weights: all of them at the list's width (the
-    bit length of its largest weight), back to back."""
+    """Words of each list's weights: in every block, the block's weights at
+    the list's weight width (the bit length of its largest weight), rounded
+    up to whole words."""
     V = rp.shape[0] - 1
     words = np.zeros(V, dtype=np.int64)
     for u in range(V):
         ws = [int(x) for x in w[int(rp[u]):int(rp[u + 1])]]
         ww = max(ws, default=0).bit_length()
-        words[u] = (len(ws) * ww + 31) // 32
+        words[u] = sum((len(ws[k:k + 64]) * ww + 31) // 32 for k in range(0, len(ws), 64))
     return words
 
 
