@@ -209,6 +209,10 @@ struct PackedCol {
 };
 template <class ColT>
 constexpr bool kPacked = std::is_same<ColT, PackedCol>::value;
+// V5 chunks loaded per group: a packed block is a short read, so packed
+// scans keep twice as many in flight per wave.
+template <class ColT>
+constexpr int kGroupChunks = kPacked<ColT> ? 8 : 4;
 
 // Words of a full packed block: first id, 63 gaps of w bits, 64 weights of ww bits.
 __device__ __forceinline__ uint32_t packed_block_words(uint32_t w, uint32_t ww) {
@@ -436,20 +440,21 @@ struct ChunkCursor {
     uint32_t wwidth;         // packed: weight width (0: no weights)
 };
 
-// kUnroll chunks' neighbours (and weights), loaded, not yet visited.
+// U chunks' neighbours (and weights), loaded, not yet visited.
+template <int U>
 struct ChunkGroup {
-    uint32_t v[kUnroll];
-    bool ok[kUnroll];
+    uint32_t v[U];
+    bool ok[U];
     // wave-uniform per chunk: the source value, where lane 0's weight is
     // (SSSP reads lane l's at wbase + l only if needed), and the tier flag
-    uint32_t uv[kUnroll];
-    uint64_t wbase[kUnroll];
-    bool tier[kUnroll];
+    uint32_t uv[U];
+    uint64_t wbase[U];
+    bool tier[U];
     // packed lists: the word after v[i] (when the gap straddles it), then the
     // bit shifts and widths of the gap (bits 0-15) and of the weight (16-31),
     // decoded once the loads are back; SSSP: the weight's words likewise
-    uint32_t hi[kUnroll], shw[kUnroll];
-    uint32_t wv[kUnroll], whi[kUnroll];
+    uint32_t hi[U], shw[U];
+    uint32_t wv[U], whi[U];
 };
 
 template <class ColT, int A>
@@ -482,14 +487,16 @@ __device__ __forceinline__ void open_run(ChunkCursor<ColT> &c, const ScanArgs &s
     enter_entry<ColT, A>(c, s, a);
 }
 
-// Issues the loads of the next kUnroll chunks (those left in the run) and
+// Issues the loads of the next U chunks (those left in the run) and
 // moves the cursor past them, to the next run when this one is done.
 template <class ColT, int A>
-__device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, const ScanArgs &s, const OpArgs &a,
+__device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGroupChunks<ColT>> &g, const ScanArgs &s,
+                                           const OpArgs &a,
                                            int lane, uint64_t &edges, uint64_t &reqb, uint64_t &verts,
                                            uint64_t &tedges, uint64_t &pkb) {
+    constexpr int U = kGroupChunks<ColT>;
 #pragma unroll
-    for (int i = 0; i < kUnroll; ++i) {
+    for (int i = 0; i < U; ++i) {
         const uint64_t kk = c.kb + i;
         g.ok[i] = false;
         g.v[i] = 0;
@@ -563,7 +570,7 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
     }
     if constexpr (kPacked<ColT>) {
 #pragma unroll
-        for (int i = 0; i < kUnroll; ++i) {
+        for (int i = 0; i < U; ++i) {
             const uint32_t sh = g.shw[i] & 0xFFu, w = (g.shw[i] >> 8) & 0xFFu;
             uint32_t x = g.v[i];
             if (lane != 0) {
@@ -578,16 +585,17 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup &g, 
             }
         }
     }
-    c.kb += kUnroll;
+    c.kb += U;
     if (c.kb >= c.kend) open_run<ColT, A>(c, s, a, c.run0 + c.stride);
 }
 
-// V5 main loop: load kUnroll chunks, then visit their neighbours.  (Keeping
+// V5 main loop: load U chunks, then visit their neighbours.  (Keeping
 // the next group's loads in flight during the visits measured no faster:
 // vector loads return in issue order, so the visits' HBM loads wait for them.)
 template <class ColT, int A>
 __device__ __forceinline__ void balanced_body(const ScanArgs &s0, const OpArgs &a,
                                               uint32_t (*seg)[kSegCap]) {
+    constexpr int U = kGroupChunks<ColT>;
     const ScanArgs s = resolved(s0);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
@@ -597,10 +605,10 @@ __device__ __forceinline__ void balanced_body(const ScanArgs &s0, const OpArgs &
     c.stride = uint64_t(gridDim.x) * kWavesPerBlock * kChunksPerWave;
     open_run<ColT, A>(c, s, a, (uint64_t(blockIdx.x) * kWavesPerBlock + wid) * kChunksPerWave);
     while (c.kb < c.kend) {
-        ChunkGroup g;
+        ChunkGroup<U> g;
         load_group<ColT, A>(c, g, s, a, lane, edges, reqb, verts, tedges, pkb);
 #pragma unroll
-        for (int i = 0; i < kUnroll; ++i) {
+        for (int i = 0; i < U; ++i) {
             int r = 0;
             if (g.ok[i]) {
                 if constexpr (kPacked<ColT>)
@@ -646,6 +654,7 @@ struct PrArgs {
 
 template <class ColT>
 __global__ __launch_bounds__(kBlock) void k_pr_pull(ScanArgs s, PrArgs pa) {
+    constexpr int U = kGroupChunks<ColT>;
     const int lane = lane_id();
     OpArgs a{};  // the cursor reads only source_value<A_LINK>, which is the vertex id
     uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, pkb = 0;
@@ -654,10 +663,10 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull(ScanArgs s, PrArgs pa) {
     c.stride = uint64_t(gridDim.x) * kWavesPerBlock * kChunksPerWave;
     open_run<ColT, A_LINK>(c, s, a, (uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * kChunksPerWave);
     while (c.kb < c.kend) {
-        ChunkGroup g;
+        ChunkGroup<U> g;
         load_group<ColT, A_LINK>(c, g, s, a, lane, edges, reqb, verts, tedges, pkb);
 #pragma unroll
-        for (int i = 0; i < kUnroll; ++i) {
+        for (int i = 0; i < U; ++i) {
             const uint64_t x = (g.ok[i] && g.v[i] < s.n) ? pa.contrib[g.v[i]] : 0ull;
             const uint64_t sum = wave_sum64(x);
             if (lane == 0 && sum) atomicAdd(&pa.acc[g.uv[i]], (unsigned long long)sum);
@@ -937,7 +946,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_sample_packed(const uint64_t *row
                                                              const uint64_t *pk_off, const uint8_t *pk_width,
                                                              uint64_t V, uint32_t *parent,
                                                              unsigned long long *ctr) {
-    uint64_t edges = 0;
+    uint64_t edges = 0, pkb = 0;
     for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
          v += uint64_t(gridDim.x) * blockDim.x) {
         const uint64_t d = row_ptr[v + 1] - row_ptr[v];
@@ -947,6 +956,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_sample_packed(const uint64_t *row
         const uint32_t w = pk_width[v];
         uint32_t x = pk[w0];
         if (x < V) uf_link(parent, uint32_t(v), x);
+        pkb += 4 + (n > 1 && w ? 4 * ((uint64_t(n - 1) * w + 31) / 32) : 0);
         for (uint32_t r = 1; r < n; ++r) {
             const uint64_t o = uint64_t(r - 1) * w;
             const uint64_t wd = w0 + 1 + (o >> 5);
@@ -959,7 +969,9 @@ __global__ __launch_bounds__(kBlock) void k_cc_sample_packed(const uint64_t *row
         edges += n;
     }
     edges = wave_sum64(edges);
+    pkb = wave_sum64(pkb);
     if (lane_id() == 0 && edges) atomicAdd(&ctr[C_EDGES], (unsigned long long)edges);
+    if (lane_id() == 0 && pkb) atomicAdd(&ctr[C_PKBYTES], (unsigned long long)pkb);
 }
 
 __global__ void k_compress(uint32_t *parent, uint64_t V) {
@@ -1237,6 +1249,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     uint64_t n;
     bool identity = false;
     int kalgo = algo;  // the operation the scan kernels run (A_LINK for sampled CC)
+    uint64_t packed_bytes = 0;  // encoded bytes of the packed lists scanned
     if (V > 0) {
         if (algo == A_CC && g->cc_sampled) {
             // sampled union-find: hook, compress, find the large tree, then one
@@ -1316,6 +1329,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
             S.edges_scanned += p.host_counters[C_EDGES];
             S.tier_edges += p.host_counters[C_TIER];
+            packed_bytes += p.host_counters[C_PKBYTES];
             std::sort(roots.begin(), roots.end());
             uint32_t big = roots[0], best = 0;
             for (size_t i = 0, j; i < roots.size(); i = j) {
@@ -1363,7 +1377,6 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     int cur = 0;
     uint32_t iter = 0;
     bool overflow_seen = false;
-    uint64_t packed_bytes = 0;  // encoded bytes of the packed lists scanned
     // The next frontier is listed from a bitmap (ordered) for BFS and CC label
     // propagation when asked, and always for SSSP, whose marks also hold the
     // improved vertices that wait for a later distance band.
