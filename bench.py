@@ -433,7 +433,13 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         # packed lists (the compression Sec. 6 proposes): the same graph with
         # ids and weights bit-packed per list, every source of the step
         t0 = time.perf_counter()
-        P = E.Graph(rp, col, w, symmetric=True, borrow=True, pack=True)
+        try:
+            P = E.Graph(rp, col, w, symmetric=True, borrow=True, pack=True)
+        except E.EmogiError as e:  # e.g. no room to pin the packed copy beside the plain arrays
+            arms["packed"] = {"status": str(e)}
+            log(f"[bench] arm packed: {arms['packed']}")
+            result["arms"] = arms
+            return result
         create_s = time.perf_counter() - t0
         P.set_scheduler("heuristic")
         ids_b, w_b = P.packed_bytes()
