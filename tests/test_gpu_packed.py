@@ -140,6 +140,15 @@ def test_packed_link_bytes(gpu_device):
         # weights 1..255: at most 8 bits each, each list rounded up to a word
         assert G.packed_bytes()[1] <= g.num_edges + 3 * int((g.degrees() > 0).sum())
         assert set(st["level_variant"]) == {5}
+        # a fixed plain variant or the probe scheduler still scans packed lists with V5
+        for mode in (2, 4, "probe"):
+            if isinstance(mode, int):
+                G.set_variant(mode)
+            else:
+                G.set_scheduler(mode)
+            G.bfs(s, out)
+            np.testing.assert_array_equal(E.to_u32(out), lv)
+            assert set(G.stats()["level_variant"]) == {5}, mode
 
 
 def test_packed_wide_gaps(gpu_device):
