@@ -462,7 +462,7 @@ def test_stats_account_for_edges(gpu_device):
         G.set_cc_algorithm("label_propagation")
         G.cc(out)
         st = G.stats()
-        assert st["edges_scanned"] >= g.num_edges  # round 1 streams every list
+        assert st["edges_scanned"] >= g.num_edges  # the first round streams every list
         G.set_cc_algorithm("sampled_union_find")
         G.cc(out)
         st = G.stats()
