@@ -107,7 +107,8 @@ def kernel_key(algo, variant, col_bytes, packed=False):
 
 
 KERNEL_SOURCES = ["paper_2006_06890_amd/csrc/traverse.hip", "paper_2006_06890_amd/csrc/wave.h",
-                  "paper_2006_06890_amd/csrc/internal.h", "paper_2006_06890_amd/csrc/tier.h"]
+                  "paper_2006_06890_amd/csrc/internal.h", "paper_2006_06890_amd/csrc/tier.h",
+                  "paper_2006_06890_amd/csrc/packed.h"]
 
 
 def counters_path(args):

@@ -171,8 +171,8 @@ emogi_status_t emogi_host_free(void *p);
  * col and weights are read only during creation.  BFS, SSSP, CC and
  * PageRank scan packed lists with the edge-balanced variant (V5) whatever
  * the scheduler; SSSP then reads each scanned list's packed weights whole.
- * Batched traversal and the HBM tier are EMOGI_E_UNSUPPORTED on packed
- * graphs.
+ * Batched traversal decodes the same blocks.  The HBM tier is
+ * EMOGI_E_UNSUPPORTED on packed graphs.
  * Nothing is leaked on failure; *out is set only on success. */
 emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t num_vertices,
                                   const void *col, uint32_t col_bytes,

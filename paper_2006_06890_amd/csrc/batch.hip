@@ -14,6 +14,7 @@
 // one hipGraph and replayed without a host round trip per level; a step whose
 // frontier is empty does nothing, so over-running the last level is harmless.
 #include "internal.h"
+#include "packed.h"
 #include "tier.h"
 #include "wave.h"
 
@@ -35,7 +36,8 @@ enum BatchCounter : int {
     B_BMIN = 9,          // SSSP: 2^32 - smallest distance left pending beyond the band (0: none)
     B_SPLIT = 10,        // SSSP: the band's upper end, shared by all sources
     B_REFILL = 11,       // SSSP: 1 when the next step starts by listing waiting sources
-    B_COUNT = 12
+    B_PKB = 12,          // packed lists: encoded bytes of the lists expanded
+    B_COUNT = 13
 };
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
@@ -60,15 +62,41 @@ struct BatchArgs {
     uint32_t hub_degree;
     TierView tier;                     // HBM copies of hub lists (tier.bits null: none)
     uint32_t delta;                    // SSSP band width (0: one band)
+    const uint32_t *pk;                // packed lists (EMOGI_F_PACK), or null
+    const uint64_t *pk_off;
+    const uint8_t *pk_width, *pk_wwidth;
 };
+
+// A packed list's blocks (wave-uniform): first word, gap and weight widths,
+// words per full block, and the encoded bytes a scan of it reads (its
+// weights only when the scan uses them).
+struct PackedList {
+    uint64_t w0;
+    uint32_t w, ww, full;
+    uint64_t bytes;
+};
+
+__device__ __forceinline__ PackedList packed_list(const BatchArgs &a, uint32_t u, uint64_t d, bool weights) {
+    PackedList L;
+    L.w0 = uniform64(a.pk_off[u]);
+    L.w = uniform32(a.pk_width[u]);
+    L.ww = a.pk_wwidth ? uniform32(a.pk_wwidth[u]) : 0u;
+    L.full = packed_block_words(L.w, L.ww);
+    const uint64_t words = uniform64(a.pk_off[u + 1]) - L.w0;
+    L.bytes = 4 * (weights ? words : words - packed_weight_words(d, L.ww));
+    return L;
+}
 
 
 // Folds a kernel's expanded-edge counts into the batch counters.
-__device__ __forceinline__ void batch_count(const BatchArgs &a, int lane, uint64_t edges, uint64_t tedges) {
+__device__ __forceinline__ void batch_count(const BatchArgs &a, int lane, uint64_t edges, uint64_t tedges,
+                                            uint64_t pkb) {
     edges = wave_sum64(edges);
     tedges = wave_sum64(tedges);
+    pkb = wave_sum64(pkb);
     if (lane == 0 && edges) atomicAdd(&a.ctr[B_EDGES], (unsigned long long)edges);
     if (lane == 0 && tedges) atomicAdd(&a.ctr[B_TIER], (unsigned long long)tedges);
+    if (lane == 0 && pkb) atomicAdd(&a.ctr[B_PKB], (unsigned long long)pkb);
 }
 
 // Pushes v (when `push`) to the short or hub queue by its degree.
@@ -179,35 +207,51 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_short(BatchArgs a) {
     const ColT *col = static_cast<const ColT *>(a.col);
     const uint64_t n = a.ctr[B_Q0 + a.cur];
     const uint32_t level = uint32_t(a.ctr[B_LEVEL]) + 1;
-    uint64_t edges = 0, tedges = 0;
+    uint64_t edges = 0, tedges = 0, pkb = 0;
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t q = uint64_t(blockIdx.x) * kWavesPerBlock + wid; q < n; q += nw) {
         const uint32_t u = uniform32(a.q[q]);
         const uint64_t b = uniform64(a.row_ptr[u]), e = uniform64(a.row_ptr[u + 1]);
         const unsigned long long fm = uniform64(a.front[u]);
-        const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
-        if (lane == 0) {
-            edges += e - b;
-            if (src.tier) tedges += e - b;
-        }
-        for (uint64_t j0 = b & ~a.align_mask; j0 < e; j0 += uint64_t(kWave) * kBUnroll) {
-            uint32_t v[kBUnroll];
-            bool ok[kBUnroll];
-#pragma unroll
-            for (int k = 0; k < kBUnroll; ++k) {
-                const uint64_t j = j0 + uint64_t(k) * kWave + lane;
-                ok[k] = j >= b && j < e;
-                v[k] = ok[k] ? uint32_t(src.col[j - src.shift]) : 0u;
+        if constexpr (kPacked<ColT>) {
+            // one decoded block of 64 ids at a time
+            const PackedList L = packed_list(a, u, e - b, false);
+            if (lane == 0) {
+                edges += e - b;
+                pkb += L.bytes;
             }
+            for (uint64_t k = 0; k * kWave < e - b; ++k) {
+                const uint64_t rest = e - b - k * kWave;
+                const uint32_t cnt = rest < uint64_t(kWave) ? uint32_t(rest) : uint32_t(kWave);
+                const uint32_t v = packed_block(a.pk, L.w0 + k * L.full, L.w, L.ww, cnt, lane, nullptr);
+                const bool p = uint32_t(lane) < cnt && bfs_visit(a, fm, v, level);
+                push_vertex(a, st, p, v, lane);
+            }
+        } else {
+            const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
+            if (lane == 0) {
+                edges += e - b;
+                if (src.tier) tedges += e - b;
+            }
+            for (uint64_t j0 = b & ~a.align_mask; j0 < e; j0 += uint64_t(kWave) * kBUnroll) {
+                uint32_t v[kBUnroll];
+                bool ok[kBUnroll];
 #pragma unroll
-            for (int k = 0; k < kBUnroll; ++k) {
-                const bool p = ok[k] && bfs_visit(a, fm, v[k], level);
-                push_vertex(a, st, p, v[k], lane);
+                for (int k = 0; k < kBUnroll; ++k) {
+                    const uint64_t j = j0 + uint64_t(k) * kWave + lane;
+                    ok[k] = j >= b && j < e;
+                    v[k] = ok[k] ? uint32_t(src.col[j - src.shift]) : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < kBUnroll; ++k) {
+                    const bool p = ok[k] && bfs_visit(a, fm, v[k], level);
+                    push_vertex(a, st, p, v[k], lane);
+                }
             }
         }
     }
     finish_queue(st, a.nq, &a.ctr[B_Q0 + (a.cur ^ 1)], lane, wid);
-    batch_count(a, lane, edges, tedges);
+    batch_count(a, lane, edges, tedges, pkb);
 }
 
 template <class ColT>
@@ -218,34 +262,50 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_hub(BatchArgs a) {
     const ColT *col = static_cast<const ColT *>(a.col);
     const uint64_t n = a.ctr[B_H0 + a.cur];
     const uint32_t level = uint32_t(a.ctr[B_LEVEL]) + 1;
-    uint64_t edges = 0, tedges = 0;
+    uint64_t edges = 0, tedges = 0, pkb = 0;
     for (uint64_t q = blockIdx.x; q < n; q += gridDim.x) {
         const uint32_t u = uniform32(a.h[q]);
         const uint64_t b = uniform64(a.row_ptr[u]), e = uniform64(a.row_ptr[u + 1]);
         const unsigned long long fm = uniform64(a.front[u]);
-        const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
-        if (lane == 0 && wid == 0) {
-            edges += e - b;
-            if (src.tier) tedges += e - b;
-        }
-        for (uint64_t j0 = b & ~a.align_mask; j0 < e; j0 += uint64_t(kBlock) * 2) {
-            uint32_t v[2];
-            bool ok[2];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const uint64_t j = j0 + uint64_t(k) * kBlock + uint64_t(wid) * kWave + lane;
-                ok[k] = j >= b && j < e;
-                v[k] = ok[k] ? uint32_t(src.col[j - src.shift]) : 0u;
+        if constexpr (kPacked<ColT>) {
+            // the workgroup's waves take the list's blocks in turn
+            const PackedList L = packed_list(a, u, e - b, false);
+            if (lane == 0 && wid == 0) {
+                edges += e - b;
+                pkb += L.bytes;
             }
+            for (uint64_t k = wid; k * kWave < e - b; k += kWavesPerBlock) {
+                const uint64_t rest = e - b - k * kWave;
+                const uint32_t cnt = rest < uint64_t(kWave) ? uint32_t(rest) : uint32_t(kWave);
+                const uint32_t v = packed_block(a.pk, L.w0 + k * L.full, L.w, L.ww, cnt, lane, nullptr);
+                const bool p = uint32_t(lane) < cnt && bfs_visit(a, fm, v, level);
+                push_vertex(a, st, p, v, lane);
+            }
+        } else {
+            const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
+            if (lane == 0 && wid == 0) {
+                edges += e - b;
+                if (src.tier) tedges += e - b;
+            }
+            for (uint64_t j0 = b & ~a.align_mask; j0 < e; j0 += uint64_t(kBlock) * 2) {
+                uint32_t v[2];
+                bool ok[2];
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const bool p = ok[k] && bfs_visit(a, fm, v[k], level);
-                push_vertex(a, st, p, v[k], lane);
+                for (int k = 0; k < 2; ++k) {
+                    const uint64_t j = j0 + uint64_t(k) * kBlock + uint64_t(wid) * kWave + lane;
+                    ok[k] = j >= b && j < e;
+                    v[k] = ok[k] ? uint32_t(src.col[j - src.shift]) : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const bool p = ok[k] && bfs_visit(a, fm, v[k], level);
+                    push_vertex(a, st, p, v[k], lane);
+                }
             }
         }
     }
     finish_queue(st, a.nq, &a.ctr[B_Q0 + (a.cur ^ 1)], lane, wid);
-    batch_count(a, lane, edges, tedges);
+    batch_count(a, lane, edges, tedges, pkb);
 }
 
 // SSSP: lane s of the wave is source s.  The wave loads 64 (neighbour,
@@ -312,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_bsssp_short(BatchArgs a) {
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(a.col);
     const uint64_t n = a.ctr[B_Q0 + a.cur];
-    uint64_t edges = 0, tedges = 0;
+    uint64_t edges = 0, tedges = 0, pkb = 0;
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t q = uint64_t(blockIdx.x) * kWavesPerBlock + wid; q < n; q += nw) {
         const uint32_t u = uniform32(a.q[q]);
@@ -320,21 +380,36 @@ __global__ __launch_bounds__(kBlock) void k_bsssp_short(BatchArgs a) {
         const uint32_t du = a.out[uint64_t(u) * 64 + lane];
         const unsigned long long fm = sssp_ready(a, u, uniform64(a.front[u]), du, lane, true);
         if (!fm) continue;
-        const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
-        if (lane == 0) {
-            edges += e - b;
-            if (src.tier) tedges += e - b;
-        }
-        for (uint64_t j0 = b & ~a.align_mask; j0 < e; j0 += kWave) {
-            const uint64_t j = j0 + lane;
-            const bool ok = j >= b && j < e;
-            const uint32_t vl = ok ? uint32_t(src.col[j - src.shift]) : 0u;
-            const uint32_t wl = ok ? src.w[j - src.shift] : 0u;
-            sssp_relax_chunk(a, st, lane, fm, du, vl, wl, ok);
+        if constexpr (kPacked<ColT>) {
+            const PackedList L = packed_list(a, u, e - b, true);
+            if (lane == 0) {
+                edges += e - b;
+                pkb += L.bytes;
+            }
+            for (uint64_t k = 0; k * kWave < e - b; ++k) {
+                const uint64_t rest = e - b - k * kWave;
+                const uint32_t cnt = rest < uint64_t(kWave) ? uint32_t(rest) : uint32_t(kWave);
+                uint32_t wl = 0;
+                const uint32_t vl = packed_block(a.pk, L.w0 + k * L.full, L.w, L.ww, cnt, lane, &wl);
+                sssp_relax_chunk(a, st, lane, fm, du, vl, wl, uint32_t(lane) < cnt);
+            }
+        } else {
+            const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
+            if (lane == 0) {
+                edges += e - b;
+                if (src.tier) tedges += e - b;
+            }
+            for (uint64_t j0 = b & ~a.align_mask; j0 < e; j0 += kWave) {
+                const uint64_t j = j0 + lane;
+                const bool ok = j >= b && j < e;
+                const uint32_t vl = ok ? uint32_t(src.col[j - src.shift]) : 0u;
+                const uint32_t wl = ok ? src.w[j - src.shift] : 0u;
+                sssp_relax_chunk(a, st, lane, fm, du, vl, wl, ok);
+            }
         }
     }
     finish_queue(st, a.nq, &a.ctr[B_Q0 + (a.cur ^ 1)], lane, wid);
-    batch_count(a, lane, edges, tedges);
+    batch_count(a, lane, edges, tedges, pkb);
 }
 
 template <class ColT>
@@ -344,28 +419,43 @@ __global__ __launch_bounds__(kBlock) void k_bsssp_hub(BatchArgs a) {
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(a.col);
     const uint64_t n = a.ctr[B_H0 + a.cur];
-    uint64_t edges = 0, tedges = 0;
+    uint64_t edges = 0, tedges = 0, pkb = 0;
     for (uint64_t q = blockIdx.x; q < n; q += gridDim.x) {
         const uint32_t u = uniform32(a.h[q]);
         const uint64_t b = uniform64(a.row_ptr[u]), e = uniform64(a.row_ptr[u + 1]);
         const uint32_t du = a.out[uint64_t(u) * 64 + lane];
         const unsigned long long fm = sssp_ready(a, u, uniform64(a.front[u]), du, lane, wid == 0);
         if (!fm) continue;
-        const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
-        if (lane == 0 && wid == 0) {
-            edges += e - b;
-            if (src.tier) tedges += e - b;
-        }
-        for (uint64_t j0 = (b & ~a.align_mask) + uint64_t(wid) * kWave; j0 < e; j0 += kBlock) {
-            const uint64_t j = j0 + lane;
-            const bool ok = j >= b && j < e;
-            const uint32_t vl = ok ? uint32_t(src.col[j - src.shift]) : 0u;
-            const uint32_t wl = ok ? src.w[j - src.shift] : 0u;
-            sssp_relax_chunk(a, st, lane, fm, du, vl, wl, ok);
+        if constexpr (kPacked<ColT>) {
+            const PackedList L = packed_list(a, u, e - b, true);
+            if (lane == 0 && wid == 0) {
+                edges += e - b;
+                pkb += L.bytes;
+            }
+            for (uint64_t k = wid; k * kWave < e - b; k += kWavesPerBlock) {
+                const uint64_t rest = e - b - k * kWave;
+                const uint32_t cnt = rest < uint64_t(kWave) ? uint32_t(rest) : uint32_t(kWave);
+                uint32_t wl = 0;
+                const uint32_t vl = packed_block(a.pk, L.w0 + k * L.full, L.w, L.ww, cnt, lane, &wl);
+                sssp_relax_chunk(a, st, lane, fm, du, vl, wl, uint32_t(lane) < cnt);
+            }
+        } else {
+            const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
+            if (lane == 0 && wid == 0) {
+                edges += e - b;
+                if (src.tier) tedges += e - b;
+            }
+            for (uint64_t j0 = (b & ~a.align_mask) + uint64_t(wid) * kWave; j0 < e; j0 += kBlock) {
+                const uint64_t j = j0 + lane;
+                const bool ok = j >= b && j < e;
+                const uint32_t vl = ok ? uint32_t(src.col[j - src.shift]) : 0u;
+                const uint32_t wl = ok ? src.w[j - src.shift] : 0u;
+                sssp_relax_chunk(a, st, lane, fm, du, vl, wl, ok);
+            }
         }
     }
     finish_queue(st, a.nq, &a.ctr[B_Q0 + (a.cur ^ 1)], lane, wid);
-    batch_count(a, lane, edges, tedges);
+    batch_count(a, lane, edges, tedges, pkb);
 }
 
 // Clears the masks of the vertices just expanded (they become the next
@@ -537,16 +627,12 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
         set_error("batched traversal needs 1..64 sources and an output");
         return EMOGI_E_INVALID;
     }
-    if (g->packed.stream) {
-        set_error("batched traversal reads plain lists; this graph's lists are packed");
-        return EMOGI_E_UNSUPPORTED;
-    }
     for (uint32_t i = 0; i < n; ++i)
         if (srcs[i] >= g->V) {
             set_error("source %llu out of range", (unsigned long long)srcs[i]);
             return EMOGI_E_INVALID;
         }
-    if (sssp && !g->weights) {
+    if (sssp && !g->weights && !g->packed.wwidth) {
         set_error("SSSP needs edge weights");
         return EMOGI_E_INVALID;
     }
@@ -582,6 +668,10 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
     a.tier = tier_view(g);
     a.hub_degree = P.hub_degree;
     a.delta = sssp ? P.sssp_delta : 0;
+    a.pk = g->packed.stream;
+    a.pk_off = g->packed.off;
+    a.pk_width = g->packed.width;
+    a.pk_wwidth = g->packed.wwidth;
     // ---- init ----
     EMOGI_HIP_TRY(hipMemcpyAsync(b.srcs, srcs, n * sizeof(uint64_t), hipMemcpyHostToDevice, s), EMOGI_E_HIP);
     hipLaunchKernelGGL(k_bfill64, dim3(grid_for(B_COUNT)), dim3(256), 0, s, b.ctr, uint64_t(B_COUNT));
@@ -622,7 +712,8 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
     const bool u64col = g->col_bytes == 8;
     auto enqueue_steps = [&]() {
         for (uint32_t k = 0; k < K; ++k) {
-            if (u64col) launch_step<uint64_t>(step[k & 1], sssp, grid, s);
+            if (g->packed.stream) launch_step<PackedCol>(step[k & 1], sssp, grid, s);
+            else if (u64col) launch_step<uint64_t>(step[k & 1], sssp, grid, s);
             else launch_step<uint32_t>(step[k & 1], sssp, grid, s);
         }
     };
@@ -702,8 +793,13 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
     S.iterations = uint32_t(levels);
     S.edges_scanned = edges;
     S.tier_edges = b.host_ctr[B_TIER];
-    S.weights_read = sssp ? edges - S.tier_edges : 0;  // every weight of a scanned list
-    S.useful_link_bytes = (edges - S.tier_edges) * g->col_bytes + S.weights_read * 4;
+    if (g->packed.stream) {
+        S.weights_read = 0;  // weights come packed inside the blocks
+        S.useful_link_bytes = b.host_ctr[B_PKB];
+    } else {
+        S.weights_read = sssp ? edges - S.tier_edges : 0;  // every weight of a scanned list
+        S.useful_link_bytes = (edges - S.tier_edges) * g->col_bytes + S.weights_read * 4;
+    }
     S.total_ms = ms;
     S.expand_ms = ms;
     S.expand_launches = uint32_t(steps);
@@ -756,10 +852,6 @@ emogi_status_t emogi_autotune_batch(emogi_graph_t g, int algo, const uint64_t *s
     if (!g || (algo != 0 && algo != 1)) {
         set_error("autotune: algo must be 0 (BFS) or 1 (SSSP)");
         return EMOGI_E_INVALID;
-    }
-    if (g->packed.stream) {
-        set_error("batched traversal reads plain lists; this graph's lists are packed");
-        return EMOGI_E_UNSUPPORTED;
     }
     // Candidate grid: hub threshold x level steps per replay x occupancy.
     const uint32_t hubs[] = {256, 1024, 8192};

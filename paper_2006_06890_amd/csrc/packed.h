@@ -1,0 +1,81 @@
+// Device side of the packed list format (EMOGI_F_PACK; the compression with
+// decoding on idle GPU cores that EMOGI proposes in Sec. 6).  A list is cut
+// into blocks of 64 ids; a block is its first id as a whole 32-bit word, the
+// gaps to its other ids at the list's gap width w, then (with weights) its
+// weights at the list's weight width ww, each part bit-packed into whole
+// words.  Every block but a list's last is full, so block k of a list
+// starting at word off starts at word off + k * packed_block_words(w, ww).
+#pragma once
+
+#include "internal.h"
+#include "wave.h"
+
+#include <type_traits>
+
+namespace emogi {
+
+// Tag for packed lists in the ColT slot of the kernels that read lists.
+struct PackedCol {
+    uint32_t x;
+};
+template <class ColT>
+constexpr bool kPacked = std::is_same<ColT, PackedCol>::value;
+
+// Words of a full packed block: first id, 63 gaps of w bits, 64 weights of ww bits.
+__device__ __forceinline__ uint32_t packed_block_words(uint32_t w, uint32_t ww) {
+    return 1u + (63u * w + 31u) / 32u + 2u * ww;
+}
+
+// Weight words of a packed list of d ids at weight width ww.
+__device__ __forceinline__ uint64_t packed_weight_words(uint64_t d, uint32_t ww) {
+    if (d == 0) return 0;
+    const uint64_t nb = (d + 63) / 64, last = d - (nb - 1) * 64;
+    return (nb - 1) * 2 * uint64_t(ww) + (last * ww + 31) / 32;
+}
+
+// Inclusive prefix sum over the 64 lanes (every lane calls it).
+__device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t x, int lane) {
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// The `w`-bit field at bit `sh` of the 64-bit window hi:lo.
+__device__ __forceinline__ uint32_t packed_field(uint32_t lo, uint32_t hi, uint32_t sh, uint32_t w) {
+    const uint64_t word = (uint64_t(hi) << 32) | lo;
+    return uint32_t((word >> sh) & ((uint64_t(1) << w) - 1));
+}
+
+// Loads and decodes block `wb` (its first word) of a list holding `cnt` ids
+// in it (1..64): lane l < cnt returns the block's l-th id and, when `ww` is
+// not 0 and `wt` is set, its weight.  Every lane of the wave calls it.
+__device__ __forceinline__ uint32_t packed_block(const uint32_t *pk, uint64_t wb, uint32_t w, uint32_t ww,
+                                                 uint32_t cnt, int lane, uint32_t *wt) {
+    const bool ok = uint32_t(lane) < cnt;
+    uint32_t x = 0;
+    if (ok) {
+        if (lane == 0) {
+            x = pk[wb];
+        } else if (w) {
+            const uint64_t o = uint64_t(lane - 1) * w;
+            const uint64_t wd = wb + 1 + (o >> 5);
+            const uint32_t sh = uint32_t(o & 31u);
+            x = packed_field(pk[wd], sh + w > 32u ? pk[wd + 1] : 0u, sh, w);
+        }
+    }
+    if (wt) {
+        *wt = 0;
+        if (ok && ww) {
+            const uint64_t base = wb + 1 + ((uint64_t(cnt) - 1) * w + 31) / 32;
+            const uint64_t o = uint64_t(lane) * ww;
+            const uint64_t wd = base + (o >> 5);
+            const uint32_t sh = uint32_t(o & 31u);
+            *wt = packed_field(pk[wd], sh + ww > 32u ? pk[wd + 1] : 0u, sh, ww);
+        }
+    }
+    return wave_prefix_sum(x, lane);  // first id + the gaps up to each lane
+}
+
+}  // namespace emogi

@@ -20,12 +20,12 @@
 //  * vertex state (levels, distances, labels, visited bitmap, stamps) stays
 //    in HBM; only the edge list (and weights) cross the host link.
 #include "internal.h"
+#include "packed.h"
 #include "tier.h"
 #include "wave.h"
 
 #include <algorithm>
 #include <cmath>
-#include <type_traits>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -203,30 +203,10 @@ struct ScanArgs {
     const uint8_t *pk_wwidth = nullptr;  // weight width of each packed list, bits (null: no weights)
 };
 
-// Tag for packed lists in the ColT slot of the V5 and PageRank kernels.
-struct PackedCol {
-    uint32_t x;
-};
-template <class ColT>
-constexpr bool kPacked = std::is_same<ColT, PackedCol>::value;
 // V5 chunks loaded per group: a packed block is a short read, so packed
 // scans keep twice as many in flight per wave.
 template <class ColT>
 constexpr int kGroupChunks = kPacked<ColT> ? 8 : 4;
-
-// Words of a full packed block: first id, 63 gaps of w bits, 64 weights of ww bits.
-__device__ __forceinline__ uint32_t packed_block_words(uint32_t w, uint32_t ww) {
-    return 1u + (63u * w + 31u) / 32u + 2u * ww;
-}
-
-// Inclusive prefix sum over the 64 lanes (every lane calls it).
-__device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t x, int lane) {
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-    }
-    return x;
-}
 
 __device__ __forceinline__ uint64_t request_bytes(uint64_t s, uint64_t e, uint32_t cb, uint32_t R) {
     uint64_t first = (s * cb) / R, last = (e * cb + R - 1) / R;
@@ -572,16 +552,11 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGro
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const uint32_t sh = g.shw[i] & 0xFFu, w = (g.shw[i] >> 8) & 0xFFu;
-            uint32_t x = g.v[i];
-            if (lane != 0) {
-                const uint64_t word = (uint64_t(g.hi[i]) << 32) | g.v[i];
-                x = uint32_t((word >> sh) & ((uint64_t(1) << w) - 1));
-            }
+            const uint32_t x = lane != 0 ? packed_field(g.v[i], g.hi[i], sh, w) : g.v[i];
             g.v[i] = wave_prefix_sum(x, lane);  // first id + the gaps up to each lane
             if (A == A_SSSP) {
                 const uint32_t wsh = (g.shw[i] >> 16) & 0xFFu, ww = g.shw[i] >> 24;
-                const uint64_t word = (uint64_t(g.whi[i]) << 32) | g.wv[i];
-                g.wv[i] = uint32_t((word >> wsh) & ((uint64_t(1) << ww) - 1));
+                g.wv[i] = packed_field(g.wv[i], g.whi[i], wsh, ww);
             }
         }
     }
