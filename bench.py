@@ -547,7 +547,8 @@ def main():
     args = parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              f"(sharding over several GPUs is described in the design notes, not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
