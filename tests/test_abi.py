@@ -44,3 +44,32 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(emogi, "_lib", None)
     with pytest.raises(ImportError):
         emogi.lib()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes mirror in the binding has the C struct's size and each
+    field's offset (compiled from include/emogi.h with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_2006_06890_amd import emogi
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = [("emogi_stats_t", emogi.Stats), ("emogi_link_profile_t", emogi.LinkProfile),
+             ("emogi_batch_params_t", emogi.BatchParams), ("emogi_batch_trial_t", emogi.BatchTrial),
+             ("emogi_train_config_t", emogi.TrainConfig)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "emogi.h"', "int main(void) {"]
+    expect = []
+    for cname, py in pairs:
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(py))
+        for name, _ in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {name}));')
+            expect.append(getattr(py, name).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == expect
