@@ -636,3 +636,102 @@ def test_adam_matches_definition():
     th, m, v = mlp.adam_step(theta, g, np.zeros(2), np.zeros(2), 1, lr=0.1)
     # first step: mhat = g, vhat = g^2 -> update = lr * sign(g) (up to eps)
     assert np.allclose(th, theta - 0.1 * np.sign(g), atol=1e-6)
+
+
+def adam_beta1_in_vhat(theta, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Planted mistake: v's bias correction uses beta1 instead of beta2."""
+    m = beta1 * m + (1.0 - beta1) * grad
+    v = beta2 * v + (1.0 - beta2) * grad * grad
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta1 ** t)
+    return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def _adam_vs_torch(step_fn):
+    """Five Adam steps of `step_fn` against torch.optim.Adam in fp64 on a
+    gradient that changes every step (t >= 2 is where the bias corrections
+    of m and v stop cancelling)."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(11))
+    theta0 = rng.standard_normal(40)
+    grads = [rng.standard_normal(40) * (0.1 + k) for k in range(5)]
+    p = torch.nn.Parameter(torch.tensor(theta0, dtype=torch.float64))
+    opt = torch.optim.Adam([p], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    th, m, v = theta0.copy(), np.zeros(40), np.zeros(40)
+    ok = True
+    for t, g in enumerate(grads, start=1):
+        opt.zero_grad()
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        th, m, v = step_fn(th, g, m, v, t, lr=1e-2)
+        ok &= bool(np.allclose(th, p.detach().numpy(), rtol=1e-12, atol=1e-14))
+    return ok
+
+
+def test_adam_steps_1_to_5_match_torch():
+    """Kingma & Ba (2015), Algorithm 1, as torch implements it: the oracle's
+    update equals torch's for t = 1..5; a v-hat corrected with beta1 differs
+    from t = 2 on."""
+    assert _adam_vs_torch(mlp.adam_step)
+    assert not _adam_vs_torch(adam_beta1_in_vhat)
+
+
+# ---------------------------------------------------------------------------
+# CSR validation: every rejection path returns its own code (the CSR of
+# Sec. 2.1 / Fig. 1: offsets from 0, non-decreasing; ids below V; simple
+# graphs have ascending lists without loops or repeats; undirected graphs
+# hold v->u for every u->v)
+# ---------------------------------------------------------------------------
+def _csr(rows, V=None):
+    V = len(rows) if V is None else V
+    rp = np.zeros(V + 1, dtype=np.uint64)
+    for u, r in enumerate(rows):
+        rp[u + 1] = rp[u] + len(r)
+    col = np.array([x for r in rows for x in r], dtype=np.uint64)
+    return rp, col
+
+
+def _always_valid(row_ptr, col, simple=False, symmetric=False):
+    """Planted mistake: a validator that accepts everything."""
+    return 0
+
+
+VALIDATION_CASES = [
+    # (name, row_ptr, col, simple, symmetric, expected code)
+    ("row_ptr[0] != 0", np.array([1, 2, 3], np.uint64), np.array([1, 0, 1], np.uint64), False, False, 1),
+    ("row_ptr decreases", np.array([0, 2, 1, 3], np.uint64), np.array([1, 2, 0], np.uint64), False, False, 2),
+    ("id >= V", *_csr([[1], [3], [1]]), False, False, 3),
+    ("id == V", *_csr([[1], [0, 2], [3]]), False, False, 3),
+    ("self-loop", *_csr([[0, 1], [0]]), True, False, 4),
+    ("unsorted list", *_csr([[2, 1], [0], [0]]), True, False, 5),
+    ("duplicate id", *_csr([[1, 1], [0]]), True, False, 5),
+    ("asymmetric edge", *_csr([[1, 2], [0], []]), True, True, 6),
+    ("asymmetric, last vertex", *_csr([[1], [0], [0]]), False, True, 6),
+]
+
+
+@pytest.mark.parametrize("name,rp,col,simple,symmetric,code", VALIDATION_CASES,
+                         ids=[c[0] for c in VALIDATION_CASES])
+@pytest.mark.parametrize("width", [np.uint32, np.uint64])
+def test_validate_csr_rejections(name, rp, col, simple, symmetric, code, width):
+    got = oracle.validate_csr(rp, col.astype(width), simple=simple, symmetric=symmetric)
+    assert got == code, (name, got)
+    assert _always_valid(rp, col, simple, symmetric) != code
+
+
+def test_validate_csr_accepts_and_checks_only_what_is_asked():
+    # a self-loop and an unsorted list are fine when simplicity is not asked for
+    rp, col = _csr([[0, 1], [0]])
+    assert oracle.validate_csr(rp, col) == 0
+    rp, col = _csr([[2, 1], [0], [0]])
+    assert oracle.validate_csr(rp, col) == 0
+    # directed but simple
+    rp, col = _csr([[1, 2], [], [1]])
+    assert oracle.validate_csr(rp, col, simple=True) == 0
+    # symmetric and simple, with an isolated vertex and the empty graph
+    rp, col = _csr([[1, 3], [0], [], [0]])
+    assert oracle.validate_csr(rp, col, simple=True, symmetric=True) == 0
+    rp, col = _csr([], V=0)
+    assert oracle.validate_csr(rp, col, simple=True, symmetric=True) == 0
+    # the first failed check is reported: row_ptr problems before ids
+    assert oracle.validate_csr(np.array([1, 1], np.uint64), np.array([5], np.uint64)) == 1
