@@ -119,7 +119,20 @@ typedef struct {
      * [4,8), [8,16), [16,64), [64,256), [256,4096), >=4096, 8-byte ids, weights
      * read, zero-copy placement, managed placement */
     float level_features[EMOGI_MAX_LEVEL_STATS][EMOGI_NUM_FEATURES];
-    float level_probe_ms[EMOGI_MAX_LEVEL_STATS][EMOGI_NUM_VARIANTS]; /* EMOGI_SCHED_PROBE */
+    float level_probe_ms[EMOGI_MAX_LEVEL_STATS][EMOGI_NUM_VARIANTS]; /* EMOGI_SCHED_PROBE: each
+                                    variant's level time, its preparation kernels included */
+    double prep_ms;              /* of expand_ms: the preparation kernels of the levels (the
+                                    edge-balanced variant's chunk prefix) and CC's sampling pass */
+    uint64_t reached_edges;      /* BFS, SSSP: sum of out-degrees of the reached vertices (the
+                                    TEPS numerator); CC, PageRank: all edges                   */
+    uint64_t id_sector_bytes;    /* neighbour-id bytes read over the host link at 32-byte sector
+                                    granularity (each list, or each bottom-up read, rounded out
+                                    to whole sectors)                                          */
+    uint64_t weight_sector_bytes;/* SSSP: 32-byte weight sectors holding a weight read over the
+                                    host link, x 32 (several weights of one sector count once)  */
+    uint32_t levels_by_network;  /* levels whose variant the scheduler network picked          */
+    uint32_t bottom_up_levels;   /* BFS levels run bottom-up (emogi_set_direction)             */
+    uint8_t level_direction[EMOGI_MAX_LEVEL_STATS]; /* 0 top-down, 1 bottom-up                  */
 } emogi_stats_t;
 
 /* ---- host-link calibration (the MI355X counterpart of the paper's toy 1-D
@@ -344,6 +357,36 @@ emogi_status_t emogi_autotune_batch(emogi_graph_t g, int algo, const uint64_t *s
  * would not leave 256 MiB of device memory free (no tier is then kept). */
 emogi_status_t emogi_set_hbm_tier(emogi_graph_t g, uint64_t budget_bytes, uint64_t *tier_vertices,
                                   uint64_t *tier_bytes);
+
+/* BFS level direction (direction-optimizing BFS; Sec. 6 notes that a pull
+ * over incoming lists keeps the same access pattern as the push over
+ * outgoing ones, and on an undirected graph a vertex's list is both).
+ * A top-down level expands the frontier's lists (Algorithm 1); a bottom-up
+ * level makes every unvisited vertex with edges read its own list, one
+ * 32-byte sector at a time, until it meets a vertex of the frontier, which
+ * makes it a vertex of the next level.  Levels are identical either way.
+ *   EMOGI_DIR_TOP_DOWN : every level top-down;
+ *   EMOGI_DIR_AUTO     : (default) per level, the rule of Beamer, Asanovic
+ *                        and Patterson (SC 2012): switch to bottom-up when
+ *                        the frontier's edges exceed the unvisited vertices'
+ *                        edges / alpha, back to top-down when the frontier
+ *                        holds fewer than (vertices with edges) / beta
+ *                        vertices (alpha, beta >= 1; 0 keeps the current value;
+ *                        defaults 14 and 24);
+ *   EMOGI_DIR_BOTTOM_UP: every level after the source's bottom-up.
+ * Bottom-up levels run only on graphs created with EMOGI_F_SYMMETRIC,
+ * with the ordered frontier, one level per host wait, plain (not packed)
+ * lists and a scheduler mode other than EMOGI_SCHED_PROBE; elsewhere
+ * every level is top-down.  stats.level_direction records each level. */
+#define EMOGI_DIR_TOP_DOWN 0
+#define EMOGI_DIR_AUTO 1
+#define EMOGI_DIR_BOTTOM_UP 2
+emogi_status_t emogi_set_direction(emogi_graph_t g, int mode, uint32_t alpha, uint32_t beta);
+
+/* Create-time passes of the graph: milliseconds spent computing each
+ * vertex's smallest incoming weight (the SSSP weight-read bound; 0 when it
+ * was not computed).  The pass reads col and weights once over the link. */
+emogi_status_t emogi_graph_setup_ms(emogi_graph_t g, double *in_min_ms);
 
 /* Statistics of the last traversal on this handle. */
 emogi_status_t emogi_last_stats(emogi_graph_t g, emogi_stats_t *out);

@@ -4,6 +4,7 @@
 // what lets GPU threads read it in place).
 #include "internal.h"
 
+#include <chrono>
 #include <cstdarg>
 #include <cstdlib>
 #include <cstring>
@@ -155,7 +156,7 @@ static void release(emogi_graph_s *g) {
         if (x) (void)hipFree(x);
     if (b.host_ctr) (void)hipHostFree(b.host_ctr);
     if (b.stream) (void)hipStreamDestroy(b.stream);
-    for (hipEvent_t e : {g->ev_begin, g->ev_end, g->ev_k0, g->ev_k1})
+    for (hipEvent_t e : {g->ev_begin, g->ev_end, g->ev_k0, g->ev_k1, g->ev_s0})
         if (e) (void)hipEventDestroy(e);
     delete g;
 }
@@ -205,6 +206,8 @@ static emogi_status_t compute_in_min(emogi_graph_s *g) {
         return EMOGI_E_OOM_DEVICE;
     }
     const unsigned grid = 256u * 8u;
+    (void)hipDeviceSynchronize();
+    const auto t0 = std::chrono::steady_clock::now();
     hipLaunchKernelGGL(k_in_min_init, dim3(grid), dim3(256), 0, nullptr, m, V);
     if (g->col_bytes == 8)
         hipLaunchKernelGGL(k_in_min<uint64_t>, dim3(grid), dim3(256), 0, nullptr,
@@ -215,6 +218,7 @@ static emogi_status_t compute_in_min(emogi_graph_s *g) {
     hipLaunchKernelGGL(k_in_min_pack, dim3(grid), dim3(256), 0, nullptr, m, V, g->in_min);
     const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipDeviceSynchronize();
+    g->in_min_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     (void)hipFree(m);
     if (e1 != hipSuccess || e2 != hipSuccess) {
         (void)hipGetLastError();
@@ -546,9 +550,14 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
     g->flags = flags;
     g->placement = placement;
     g->device = dev;
-    uint64_t maxd = 0;
-    for (uint64_t u = 0; u < V; ++u) maxd = std::max(maxd, row_ptr[u + 1] - row_ptr[u]);
+    uint64_t maxd = 0, nz = 0;
+    for (uint64_t u = 0; u < V; ++u) {
+        const uint64_t d = row_ptr[u + 1] - row_ptr[u];
+        maxd = std::max(maxd, d);
+        nz += d > 0;
+    }
     g->max_degree = maxd;
+    g->nonisolated = nz;
     // The smallest weight bounds what an edge can add to a distance: SSSP
     // skips the weight read of an edge whose target is already that close.
     g->min_weight = 0;
@@ -595,7 +604,7 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
         if (st == EMOGI_OK && E > 0 && placement == EMOGI_PLACE_HOST_ZERO_COPY) st = compute_in_min(g);
     }
     if (st == EMOGI_OK) {
-        for (hipEvent_t *e : {&g->ev_begin, &g->ev_end, &g->ev_k0, &g->ev_k1})
+        for (hipEvent_t *e : {&g->ev_begin, &g->ev_end, &g->ev_k0, &g->ev_k1, &g->ev_s0})
             if (hipEventCreate(e) != hipSuccess) {
                 (void)hipGetLastError();
                 set_error("hipEventCreate failed");
@@ -682,6 +691,26 @@ emogi_status_t emogi_set_scheduler(emogi_graph_t g, int mode) {
     }
     g->sched_mode = base;
     g->record_features = (mode & EMOGI_SCHED_RECORD) != 0;
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_set_direction(emogi_graph_t g, int mode, uint32_t alpha, uint32_t beta) {
+    if (!g || (mode != EMOGI_DIR_TOP_DOWN && mode != EMOGI_DIR_AUTO && mode != EMOGI_DIR_BOTTOM_UP)) {
+        set_error("unknown direction mode %d", mode);
+        return EMOGI_E_INVALID;
+    }
+    g->direction = mode;
+    if (alpha) g->dir_alpha = alpha;
+    if (beta) g->dir_beta = beta;
+    return EMOGI_OK;
+}
+
+emogi_status_t emogi_graph_setup_ms(emogi_graph_t g, double *in_min_ms) {
+    if (!g || !in_min_ms) {
+        set_error("null argument");
+        return EMOGI_E_INVALID;
+    }
+    *in_min_ms = g->in_min_ms;
     return EMOGI_OK;
 }
 

@@ -37,7 +37,11 @@ enum Counter : int {
     C_TIER = 15,     // edges of expanded vertices whose lists were read from the HBM tier
     C_WLINK = 16,    // SSSP: weights read over the host link
     C_PKBYTES = 17,  // packed lists: encoded bytes of the lists scanned
-    C_COUNT = 18
+    C_FEDGES = 18,   // sum of degrees of the next frontier (listing pass or bottom-up finds)
+    C_REST = 19,     // bottom-up: vertices left for the wave-per-vertex pass
+    C_IDSECT = 20,   // 32-byte sectors of neighbour ids read over the host link
+    C_WSECT = 21,    // SSSP: 32-byte sectors of weights read over the host link
+    C_COUNT = 22
 };
 
 // HBM tier of neighbour lists (device arrays; see tier.h).
@@ -87,6 +91,7 @@ struct Pool {
     uint32_t *snap_farbits = nullptr;
     uint32_t *cc_probe = nullptr;             // CC: roots of probed vertices
     uint32_t *nextbits = nullptr;             // ordered frontier bitmap (SSSP: improved, not yet expanded)
+    uint32_t *fbits = nullptr;                // bottom-up BFS: the current frontier as a bitmap
     unsigned long long *pr_acc = nullptr;     // PageRank: per-vertex sums of the iteration
     uint64_t *pr_contrib = nullptr;           // PageRank: floor(score / degree) per vertex
     unsigned long long *level_ctr = nullptr;  // BFS level batches: one counter block per level
@@ -137,6 +142,10 @@ struct emogi_graph_s {
     uint32_t min_weight = 0;       // smallest edge weight (a bound for skipping weight reads)
     uint8_t *in_min = nullptr;     // device, per vertex: smallest weight of an edge into it,
                                    // saturated at 255 (a tighter bound of the same kind)
+    double in_min_ms = 0;          // time of the pass that computed in_min (0: not computed)
+    uint64_t nonisolated = 0;      // vertices with at least one edge
+    int direction = EMOGI_DIR_AUTO; // BFS level direction policy (emogi_set_direction)
+    uint32_t dir_alpha = 14, dir_beta = 24;
 
     emogi::Pool pool;
     emogi::BatchPool batch;
@@ -145,6 +154,7 @@ struct emogi_graph_s {
     emogi_batch_params_t batch_params{1024, 4, 8, 1, 0};
     hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;
+    hipEvent_t ev_s0 = nullptr;     // before a level's preparation kernels (V5 chunk prefix)
     emogi_stats_t stats{};
 };
 

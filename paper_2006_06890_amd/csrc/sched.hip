@@ -148,7 +148,7 @@ static FeatureConsts feature_consts(const emogi_graph_s *g, int algo, uint64_t n
 }
 
 static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue,
-                        hipStream_t stream, float *features_host) {
+                        hipStream_t stream, float *features_host, int *by_network) {
     SchedScratch s;
     if (sched_scratch(g, &s) != EMOGI_OK) return -1;
     if (hipMemsetAsync(s.acc, 0, 128, stream) != hipSuccess) return -1;
@@ -170,6 +170,7 @@ static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *
     }
     if (features_host) memcpy(features_host, h.feat, sizeof(h.feat));
     if (!g->mlp_params || h.choice < 0 || h.choice >= kNOut) return heuristic_variant(g, n);  // also: outside range
+    *by_network = 1;
     return h.choice;
 }
 
@@ -208,13 +209,19 @@ emogi_status_t sched_prefetch(emogi_graph_s *g, int algo, const uint32_t *queue,
 
 // Variant for a frontier whose pick and features sched_prefetch computed
 // (hc: the host copy of the counter block).  Same rule as choose_variant.
-int choose_prefetched(const emogi_graph_s *g, uint64_t n, const unsigned long long *hc, float *features) {
+// *by_network is set to 1 when the network's pick is used.
+int choose_prefetched(const emogi_graph_s *g, uint64_t n, const unsigned long long *hc, float *features,
+                      int *by_network) {
+    *by_network = 0;
     if (features) memcpy(features, &hc[C_FEAT], kNIn * sizeof(float));
     const int m = g->sched_mode;
     if (m >= 0 && m < EMOGI_NUM_VARIANTS) return m;
     if (m == EMOGI_SCHED_LEARNED && g->mlp_params) {
         const int c = int(uint32_t(hc[C_CHOICE] & 0xFFFFFFFFull));
-        if (c >= 0 && c < kNOut) return c;
+        if (c >= 0 && c < kNOut) {
+            *by_network = 1;
+            return c;
+        }
     }
     return heuristic_variant(g, n);
 }
@@ -222,15 +229,19 @@ int choose_prefetched(const emogi_graph_s *g, uint64_t n, const unsigned long lo
 // Variant for the level; fills `features` (16 floats) when non-null.
 // Returns -1 when the scheduler's kernels fail.
 int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue, hipStream_t stream,
-                   float *features) {
+                   float *features, int *by_network) {
     const int m = g->sched_mode;
-    int learned = -2;
+    int learned = -2, net = 0;
+    *by_network = 0;
     if (features || (m == EMOGI_SCHED_LEARNED && g->mlp_params)) {
-        learned = learned_pick(g, algo, n, queue, stream, features);
+        learned = learned_pick(g, algo, n, queue, stream, features, &net);
         if (learned < 0) return -1;
     }
     if (m >= 0 && m < EMOGI_NUM_VARIANTS) return m;
-    if (m == EMOGI_SCHED_LEARNED && g->mlp_params) return learned;
+    if (m == EMOGI_SCHED_LEARNED && g->mlp_params) {
+        *by_network = net;
+        return learned;
+    }
     return heuristic_variant(g, n);
 }
 

@@ -38,33 +38,59 @@ constexpr int kUnroll = 4;        // loads in flight per lane in the wave varian
 constexpr int kChunksPerWave = 8; // V5: consecutive aligned chunks per wave visit
 constexpr int kMaxGrid = 256 * 8; // 8 blocks of 4 waves on each of the 256 CUs
 
+// Per-wave statistics of a scan, folded into the level's counters once per
+// block (lane 0 of a list or chunk adds to most fields; see count_list).
+struct Tally {
+    uint64_t edges = 0;   // ids of the expanded lists
+    uint64_t reqb = 0;    // those lists rounded out to the request unit
+    uint64_t verts = 0;   // expanded vertices
+    uint64_t tedges = 0;  // ids read from the HBM tier
+    uint64_t wlink = 0;   // SSSP: weights read over the host link
+    uint64_t pkb = 0;     // packed lists: encoded bytes scanned
+    uint64_t isect = 0;   // 32-byte sectors of ids read over the host link
+    uint64_t wsect = 0;   // 32-byte sectors of weights read over the host link
+};
+
+__device__ __forceinline__ void add_counter(unsigned long long *ctr, int c, uint64_t x) {
+    x = wave_sum64(x);
+    if (lane_id() == 0 && x) atomicAdd(&ctr[c], (unsigned long long)x);
+}
+
+__device__ __forceinline__ void flush_tally(const Tally &t, unsigned long long *ctr) {
+    add_counter(ctr, C_EDGES, t.edges);
+    add_counter(ctr, C_REQBYTES, t.reqb);
+    add_counter(ctr, C_VERTS, t.verts);
+    add_counter(ctr, C_TIER, t.tedges);
+    add_counter(ctr, C_WLINK, t.wlink);
+    add_counter(ctr, C_PKBYTES, t.pkb);
+    add_counter(ctr, C_IDSECT, t.isect);
+    add_counter(ctr, C_WSECT, t.wsect);
+}
+
 // End of a scan block: flush the staged frontier and fold the statistics.
-__device__ __forceinline__ void finish_block(Stage &st, uint32_t *next, unsigned long long *ctr,
-                                             int lane, int wid, uint64_t edges, uint64_t reqb,
-                                             uint64_t verts, uint64_t tedges, uint64_t wlink = 0,
-                                             uint64_t pkb = 0) {
+__device__ __forceinline__ void finish_block(Stage &st, uint32_t *next, unsigned long long *ctr, int lane, int wid,
+                                             const Tally &t) {
     finish_queue(st, next, &ctr[C_NEXT], lane, wid);
-    edges = wave_sum64(edges);
-    reqb = wave_sum64(reqb);
-    verts = wave_sum64(verts);
-    tedges = wave_sum64(tedges);
-    wlink = wave_sum64(wlink);
-    pkb = wave_sum64(pkb);
-    if (lane == 0) {
-        if (edges) atomicAdd(&ctr[C_EDGES], (unsigned long long)edges);
-        if (reqb) atomicAdd(&ctr[C_REQBYTES], (unsigned long long)reqb);
-        if (verts) atomicAdd(&ctr[C_VERTS], (unsigned long long)verts);
-        if (tedges) atomicAdd(&ctr[C_TIER], (unsigned long long)tedges);
-        if (wlink) atomicAdd(&ctr[C_WLINK], (unsigned long long)wlink);
-        if (pkb) atomicAdd(&ctr[C_PKBYTES], (unsigned long long)pkb);
-    }
+    flush_tally(t, ctr);
+}
+
+// Number of 32-byte sectors holding the 4-byte elements of the lanes in m,
+// lane l's element at byte address base + 4 l (consecutive lanes, so the
+// mask shifted by base's position inside its sector has one byte per sector).
+__device__ __forceinline__ uint32_t sectors_of(uint64_t m, uint64_t base) {
+    if (!m) return 0;
+    const uint32_t off = uint32_t(base >> 2) & 7u;
+    const uint64_t hi = off ? (m >> (64 - off)) : 0;
+    uint64_t x = m << off;
+    x |= x >> 4;
+    x |= x >> 2;
+    x |= x >> 1;
+    return uint32_t(__popcll(x & 0x0101010101010101ull)) + (hi ? 1u : 0u);
 }
 
 // Per-list statistics: every expanded list counts its edges; a list read over
 // the host link also counts its request-granular bytes, a tier list its edges.
-__device__ __forceinline__ void count_list(bool tier, uint64_t b, uint64_t e, uint32_t cb, uint32_t R,
-                                           uint64_t &edges, uint64_t &reqb, uint64_t &verts,
-                                           uint64_t &tedges);
+__device__ __forceinline__ void count_list(bool tier, uint64_t b, uint64_t e, uint32_t cb, uint32_t R, Tally &t);
 
 // ---------------------------------------------------------------------------
 // Application step per neighbour (Algorithm 1's workload + condition).
@@ -213,27 +239,29 @@ __device__ __forceinline__ uint64_t request_bytes(uint64_t s, uint64_t e, uint32
     return (last - first) * R;
 }
 
-__device__ __forceinline__ void count_list(bool tier, uint64_t b, uint64_t e, uint32_t cb, uint32_t R,
-                                           uint64_t &edges, uint64_t &reqb, uint64_t &verts,
-                                           uint64_t &tedges) {
-    edges += e - b;
-    verts += 1;
-    if (tier) tedges += e - b;
-    else reqb += request_bytes(b, e, cb, R);
+__device__ __forceinline__ void count_list(bool tier, uint64_t b, uint64_t e, uint32_t cb, uint32_t R, Tally &t) {
+    t.edges += e - b;
+    t.verts += 1;
+    if (tier) {
+        t.tedges += e - b;
+    } else {
+        t.reqb += request_bytes(b, e, cb, R);
+        t.isect += request_bytes(b, e, cb, 32) / 32;
+    }
 }
 
 // A packed list [b, e) in words [w0, w1) counts its edges, its encoded
 // bytes (without its weight words unless the scan uses the weights), and
-// its words rounded out to the request unit.
+// its words rounded out to the request unit.  Its 32-byte sectors are
+// counted per block as the blocks are read (count_packed_block).
 __device__ __forceinline__ void count_packed(uint64_t b, uint64_t e, uint64_t w0, uint64_t w1, uint32_t ww,
-                                             bool weights, uint32_t R, uint64_t &edges, uint64_t &reqb,
-                                             uint64_t &verts, uint64_t &pkb) {
+                                             bool weights, uint32_t R, Tally &t) {
     const uint64_t d = e - b, nb = (d + 63) / 64, last = d - (nb - 1) * 64;
     const uint64_t wwords = (nb - 1) * 2 * uint64_t(ww) + (last * ww + 31) / 32;
-    edges += d;
-    verts += 1;
-    reqb += request_bytes(w0, w1, 4, R);
-    pkb += (w1 - w0 - (weights ? 0 : wwords)) * 4;
+    t.edges += d;
+    t.verts += 1;
+    t.reqb += request_bytes(w0, w1, 4, R);
+    t.pkb += (w1 - w0 - (weights ? 0 : wwords)) * 4;
 }
 
 __device__ __forceinline__ uint32_t frontier_at(const ScanArgs &s, uint32_t q) {
@@ -258,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s0, OpArgs a) {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(s.col);
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0;
+    Tally t;
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t q = uint64_t(blockIdx.x) * kWavesPerBlock + wid; q < s.n; q += nw) {
         const uint32_t u = uniform32(frontier_at(s, uint32_t(q)));
@@ -266,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s0, OpArgs a) {
         if (b == e) continue;
         const uint32_t uval = uniform32(source_value<A>(a, u));
         const ListSrc<ColT> src = list_src(s.tier, col, s.w, u, b);
-        if (lane == 0) count_list(src.tier, b, e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
+        if (lane == 0) count_list(src.tier, b, e, s.col_bytes, s.req_unit, t);
         const uint64_t start = ALIGN ? (b & ~s.align_mask) : b;
         for (uint64_t j0 = start; j0 < e; j0 += uint64_t(kWave) * kUnroll) {
             uint32_t v[kUnroll];
@@ -283,12 +311,18 @@ __global__ __launch_bounds__(kBlock) void k_wave(ScanArgs s0, OpArgs a) {
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
                 const int r = ok[k] ? visit<A>(a, uval, v[k], wp[k]) : 0;
-                if ((r & kWeightRead) && !src.tier) ++wlink;
+                if (A == A_SSSP && !src.tier) {
+                    const uint64_t m = __ballot(r & kWeightRead);
+                    if (lane == 0) {
+                        t.wlink += __popcll(m);
+                        t.wsect += sectors_of(m, reinterpret_cast<uint64_t>(src.w + (j0 + uint64_t(k) * kWave - src.shift)));
+                    }
+                }
                 emit<A>(st, r & 3, v[k], s.next, a, lane);
             }
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink);
+    finish_block(st, s.next, a.ctr, lane, wid, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -301,14 +335,14 @@ __global__ __launch_bounds__(kBlock) void k_block(ScanArgs s0, OpArgs a) {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
     const ColT *col = static_cast<const ColT *>(s.col);
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0;
+    Tally t;
     for (uint64_t q = blockIdx.x; q < s.n; q += gridDim.x) {
         const uint32_t u = uniform32(frontier_at(s, uint32_t(q)));
         const uint64_t b = uniform64(s.row_ptr[u]), e = uniform64(s.row_ptr[u + 1]);
         if (b == e) continue;
         const uint32_t uval = uniform32(source_value<A>(a, u));
         const ListSrc<ColT> src = list_src(s.tier, col, s.w, u, b);
-        if (lane == 0 && wid == 0) count_list(src.tier, b, e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
+        if (lane == 0 && wid == 0) count_list(src.tier, b, e, s.col_bytes, s.req_unit, t);
         const uint64_t start = b & ~s.align_mask;
         for (uint64_t j0 = start; j0 < e; j0 += uint64_t(kBlock) * 2) {
             uint32_t v[2];
@@ -325,12 +359,19 @@ __global__ __launch_bounds__(kBlock) void k_block(ScanArgs s0, OpArgs a) {
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 const int r = ok[k] ? visit<A>(a, uval, v[k], wp[k]) : 0;
-                if ((r & kWeightRead) && !src.tier) ++wlink;
+                if (A == A_SSSP && !src.tier) {
+                    const uint64_t m = __ballot(r & kWeightRead);
+                    if (lane == 0) {
+                        t.wlink += __popcll(m);
+                        t.wsect += sectors_of(m, reinterpret_cast<uint64_t>(
+                                                     src.w + (j0 + uint64_t(k) * kBlock + uint64_t(wid) * kWave - src.shift)));
+                    }
+                }
                 emit<A>(st, r & 3, v[k], s.next, a, lane);
             }
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink);
+    finish_block(st, s.next, a.ctr, lane, wid, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -347,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_group(ScanArgs s0, OpArgs a) {
     const ColT *col = static_cast<const ColT *>(s.col);
     constexpr int kGroups = kWave / G;
     const int g = lane / G, gl = lane % G;
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0;
+    Tally t;
     const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
     for (uint64_t q0 = (uint64_t(blockIdx.x) * kWavesPerBlock + wid) * kGroups; q0 < s.n;
          q0 += nw * kGroups) {
@@ -366,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_group(ScanArgs s0, OpArgs a) {
             uval = source_value<A>(a, u);
             src = list_src(s.tier, col, s.w, u, b);
         }
-        if (gl == 0 && b < e) count_list(src.tier, b, e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
+        if (gl == 0 && b < e) count_list(src.tier, b, e, s.col_bytes, s.req_unit, t);
         // G == 1: no rounding (thread walks its own list); G == 16: round to the group span.
         const uint64_t start = (G == 1) ? b : (b & ~uint64_t(G - 1));
         for (uint64_t j = start + gl; __ballot(j < e) != 0; j += G) {
@@ -374,11 +415,16 @@ __global__ __launch_bounds__(kBlock) void k_group(ScanArgs s0, OpArgs a) {
             uint32_t v = 0;
             if (ok) v = load_col(src.col, j - src.shift);
             const int r = ok ? visit<A>(a, uval, v, A == A_SSSP ? src.w + (j - src.shift) : nullptr) : 0;
-            if ((r & kWeightRead) && !src.tier) ++wlink;
+            if ((r & kWeightRead) && !src.tier) {
+                // lists of different lanes (groups) lie apart: one sector per
+                // weight (an upper bound when neighbouring lists share one)
+                ++t.wlink;
+                ++t.wsect;
+            }
             emit<A>(st, r & 3, v, s.next, a, lane);
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink);
+    finish_block(st, s.next, a.ctr, lane, wid, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -471,9 +517,7 @@ __device__ __forceinline__ void open_run(ChunkCursor<ColT> &c, const ScanArgs &s
 // moves the cursor past them, to the next run when this one is done.
 template <class ColT, int A>
 __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGroupChunks<ColT>> &g, const ScanArgs &s,
-                                           const OpArgs &a,
-                                           int lane, uint64_t &edges, uint64_t &reqb, uint64_t &verts,
-                                           uint64_t &tedges, uint64_t &pkb) {
+                                           const OpArgs &a, int lane, Tally &t) {
     constexpr int U = kGroupChunks<ColT>;
 #pragma unroll
     for (int i = 0; i < U; ++i) {
@@ -499,10 +543,9 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGro
             g.uv[i] = c.uval;
             if (kk == c.qfirst && lane == 0) {
                 if constexpr (kPacked<ColT>)
-                    count_packed(c.b, c.e, c.pw0, c.pw1, c.wwidth, A == A_SSSP, s.req_unit, edges, reqb, verts,
-                                 pkb);
+                    count_packed(c.b, c.e, c.pw0, c.pw1, c.wwidth, A == A_SSSP, s.req_unit, t);
                 else
-                    count_list(c.src.tier, c.b, c.e, s.col_bytes, s.req_unit, edges, reqb, verts, tedges);
+                    count_list(c.src.tier, c.b, c.e, s.col_bytes, s.req_unit, t);
             }
             const uint64_t j0 = uniform64((c.b & ~s.align_mask) + (kk - c.qfirst) * kWave);
             const uint64_t j = j0 + lane;
@@ -515,6 +558,16 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGro
                 // lane l the gap to id l, bits [(l-1)w, lw) after that word
                 const uint64_t wb = c.pw0 + (kk - c.qfirst) * c.pfull;
                 const uint32_t w = c.pwidth;
+                if (lane == 0) {
+                    // 32-byte sectors of the block's id words (and, for SSSP,
+                    // of the weight words right after them)
+                    const uint64_t cnt = c.e - j0 < uint64_t(kWave) ? c.e - j0 : uint64_t(kWave);
+                    const uint64_t idw = 1 + ((cnt - 1) * w + 31) / 32;
+                    const uint64_t ids = request_bytes(wb, wb + idw, 4, 32) / 32;
+                    t.isect += ids;
+                    if (A == A_SSSP)
+                        t.wsect += request_bytes(wb, wb + idw + (cnt * c.wwidth + 31) / 32, 4, 32) / 32 - ids;
+                }
                 uint32_t sh = 0;
                 if (g.ok[i]) {
                     if (lane == 0) {
@@ -574,14 +627,14 @@ __device__ __forceinline__ void balanced_body(const ScanArgs &s0, const OpArgs &
     const ScanArgs s = resolved(s0);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, wlink = 0, pkb = 0;
+    Tally t;
     ChunkCursor<ColT> c;
     c.total = s.chunk_scan[s.n];
     c.stride = uint64_t(gridDim.x) * kWavesPerBlock * kChunksPerWave;
     open_run<ColT, A>(c, s, a, (uint64_t(blockIdx.x) * kWavesPerBlock + wid) * kChunksPerWave);
     while (c.kb < c.kend) {
         ChunkGroup<U> g;
-        load_group<ColT, A>(c, g, s, a, lane, edges, reqb, verts, tedges, pkb);
+        load_group<ColT, A>(c, g, s, a, lane, t);
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             int r = 0;
@@ -591,11 +644,17 @@ __device__ __forceinline__ void balanced_body(const ScanArgs &s0, const OpArgs &
                 else
                     r = visit<A>(a, g.uv[i], g.v[i], reinterpret_cast<const uint32_t *>(g.wbase[i]) + lane);
             }
-            if ((r & kWeightRead) && !g.tier[i]) ++wlink;
+            if (A == A_SSSP && !kPacked<ColT> && !g.tier[i]) {
+                const uint64_t m = __ballot(r & kWeightRead);
+                if (lane == 0) {
+                    t.wlink += __popcll(m);
+                    t.wsect += sectors_of(m, g.wbase[i]);
+                }
+            }
             emit<A>(st, r & 3, g.v[i], s.next, a, lane);
         }
     }
-    finish_block(st, s.next, a.ctr, lane, wid, edges, reqb, verts, tedges, wlink, pkb);
+    finish_block(st, s.next, a.ctr, lane, wid, t);
 }
 
 template <class ColT, int A>
@@ -611,6 +670,196 @@ template <int A>
 __global__ __launch_bounds__(kBlock) void k_balanced_packed(ScanArgs s0, OpArgs a) {
     __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
     balanced_body<PackedCol, A>(s0, a, seg);
+}
+
+// ---------------------------------------------------------------------------
+// Bottom-up BFS levels (direction-optimizing BFS).  The paper's Sec. 6 notes
+// that a pull over incoming lists reads memory the way the push over
+// outgoing lists does; on an undirected graph a vertex's list is also its
+// list of incoming edges.  The current frontier is a bitmap (fbits); every
+// unvisited vertex with edges reads its own list until it meets a frontier
+// vertex, which puts it in the next level (there is no race: only the
+// vertex itself decides).  The reads are small and mostly one per vertex,
+// in vertex order, so they reach the host link as a dense stream of 32-byte
+// requests.
+//   k_bu_probe: a wave owns tiles of 64 consecutive vertices (two bitmap
+//     words, written back whole, without atomics).  Its candidates are
+//     compacted in LDS and served kBuLanes = 32 / sizeof(id) lanes each: a
+//     step reads the 32-byte sector of the list that holds the next ids,
+//     at most kBuProbeSectors steps; a candidate that neither found a
+//     frontier neighbour nor ran out of ids is queued for
+//   k_bu_rest: a wave per queued vertex, 64-id loads from where the probe
+//     stopped, leaving at the first frontier neighbour.
+// ---------------------------------------------------------------------------
+constexpr int kBuProbeSectors = 2;
+
+struct BuArgs {
+    const uint64_t *row_ptr;
+    const void *col;
+    TierView tier;
+    uint64_t V;
+    const uint32_t *fbits;    // the current frontier
+    uint32_t *visited;        // BFS visited bits
+    uint32_t *nextbits;       // the next frontier (marked here)
+    uint32_t *level;          // levels (the caller's output)
+    uint32_t tag;             // level of the next frontier
+    uint32_t *rest;           // vertices left by the probe (k_bu_probe writes, k_bu_rest reads)
+    unsigned long long *ctr;  // C_NEXT, C_FEDGES, C_REST, C_EDGES (ids examined), C_IDSECT,
+                              // C_REQBYTES (sectors x 32), C_TIER, C_VERTS (candidates)
+};
+
+__device__ __forceinline__ bool in_frontier(const uint32_t *fbits, uint64_t V, uint32_t x) {
+    return x < V && ((fbits[x >> 5] >> (x & 31u)) & 1u);
+}
+
+template <class ColT>
+__global__ __launch_bounds__(kBlock) void k_bu_probe(BuArgs s) {
+    constexpr int G = 32 / int(sizeof(ColT));  // lanes per candidate: one sector of ids
+    constexpr int S = kWave / G;               // candidates served per step
+    __shared__ uint32_t cand[kWavesPerBlock][kWave];
+    __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
+    __shared__ uint32_t found_w[kWavesPerBlock][2];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int slot = lane / G, gl = lane % G;
+    const uint64_t gmask = ((uint64_t(1) << G) - 1) << (slot * G);
+    Stage st{seg[wid], 0};
+    Tally t;
+    uint64_t nfound = 0, fedges = 0;
+    const ColT *col = static_cast<const ColT *>(s.col);
+    const uint64_t words = (s.V + 31) / 32, tiles = (s.V + 63) / 64;
+    for (uint64_t tile = uint64_t(blockIdx.x) * kWavesPerBlock + wid; tile < tiles;
+         tile += uint64_t(gridDim.x) * kWavesPerBlock) {
+        const uint64_t w0 = 2 * tile;
+        const uint32_t vis0 = s.visited[w0], vis1 = w0 + 1 < words ? s.visited[w0 + 1] : ~0u;
+        const uint64_t vis = uint64_t(vis0) | (uint64_t(vis1) << 32);
+        if (vis == ~uint64_t(0)) continue;  // (uniform) nothing left in the tile
+        const uint64_t v = tile * 64 + lane;
+        bool c = v < s.V && !((vis >> lane) & 1u);
+        if (c) c = s.row_ptr[v + 1] > s.row_ptr[v];
+        const uint64_t cm = __ballot(c);
+        if (!cm) continue;
+        if (c) cand[wid][rank_below(cm)] = uint32_t(v);
+        if (lane < 2) found_w[wid][lane] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t nc = uint32_t(__popcll(cm));
+        if (lane == 0) t.verts += nc;
+        for (uint32_t r0 = 0; r0 < nc; r0 += S) {
+            const uint32_t k = r0 + slot;
+            const bool has = k < nc;
+            uint32_t x = 0;
+            uint64_t b = 0, e = 0;
+            if (has) {
+                x = cand[wid][k];
+                b = s.row_ptr[x];
+                e = s.row_ptr[x + 1];
+            }
+            const ListSrc<ColT> src = has ? list_src(s.tier, col, static_cast<const uint32_t *>(nullptr), x, b)
+                                          : ListSrc<ColT>{col, nullptr, 0, false};
+            const uint64_t j0 = b & ~uint64_t(G - 1);
+            bool hit = false, more = has;
+            for (int step = 0; step < kBuProbeSectors; ++step) {
+                const uint64_t j = j0 + uint64_t(step) * G + gl;
+                const bool ok = more && j >= b && j < e;
+                uint32_t nb = 0;
+                if (ok) nb = load_col(src.col, j - src.shift);
+                const uint64_t fm = __ballot(ok && in_frontier(s.fbits, s.V, nb));
+                const uint64_t om = __ballot(ok);
+                if (gl == 0 && more) {
+                    const uint32_t n_ok = uint32_t(__popcll(om & gmask));
+                    t.edges += n_ok;
+                    if (src.tier) t.tedges += n_ok;
+                    else {
+                        t.isect += 1;
+                        t.reqb += 32;
+                    }
+                }
+                if (fm & gmask) {
+                    hit = true;
+                    more = false;
+                } else if (j0 + uint64_t(step + 1) * G >= e) {
+                    more = false;
+                }
+                if (__ballot(more) == 0) break;
+            }
+            if (gl == 0 && hit) {
+                s.level[x] = s.tag;
+                atomicOr(&found_w[wid][(x & 63u) >> 5], 1u << (x & 31u));
+                fedges += e - b;
+            }
+            // a candidate with ids left over goes to the wave-per-vertex pass
+            stage(st, gl == 0 && more, x, s.rest, &s.ctr[C_REST], lane);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t f0 = found_w[wid][0], f1 = found_w[wid][1];
+        if (lane == 0 && (f0 | f1)) {
+            nfound += __popc(f0) + __popc(f1);
+            // the wave owns both words of its tile during this kernel
+            if (f0) {
+                s.visited[w0] = vis0 | f0;
+                s.nextbits[w0] |= f0;
+            }
+            if (f1) {
+                s.visited[w0 + 1] = vis1 | f1;
+                s.nextbits[w0 + 1] |= f1;
+            }
+        }
+    }
+    finish_queue(st, s.rest, &s.ctr[C_REST], lane, wid);
+    flush_tally(t, s.ctr);
+    add_counter(s.ctr, C_NEXT, nfound);
+    add_counter(s.ctr, C_FEDGES, fedges);
+}
+
+template <class ColT>
+__global__ __launch_bounds__(kBlock) void k_bu_rest(BuArgs s) {
+    constexpr int G = 32 / int(sizeof(ColT));
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    Tally t;
+    uint64_t nfound = 0, fedges = 0;
+    const ColT *col = static_cast<const ColT *>(s.col);
+    const uint64_t n = s.ctr[C_REST];
+    const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
+    for (uint64_t q = uint64_t(blockIdx.x) * kWavesPerBlock + wid; q < n; q += nw) {
+        const uint32_t x = uniform32(s.rest[q]);
+        const uint64_t b = uniform64(s.row_ptr[x]), e = uniform64(s.row_ptr[x + 1]);
+        const ListSrc<ColT> src = list_src(s.tier, col, static_cast<const uint32_t *>(nullptr), x, b);
+        // the probe read the sectors up to `from`
+        const uint64_t from = (b & ~uint64_t(G - 1)) + uint64_t(kBuProbeSectors) * G;
+        bool hit = false;
+        for (uint64_t j0 = from & ~uint64_t(kWave - 1); j0 < e && !hit; j0 += kWave) {
+            const uint64_t j = j0 + lane;
+            const bool ok = j >= from && j < e;
+            uint32_t nb = 0;
+            if (ok) nb = load_col(src.col, j - src.shift);
+            const uint64_t om = __ballot(ok);
+            hit = __ballot(ok && in_frontier(s.fbits, s.V, nb)) != 0;
+            if (lane == 0) {
+                t.edges += __popcll(om);
+                if (src.tier) {
+                    t.tedges += __popcll(om);
+                } else {
+                    const uint64_t lo = j0 > from ? j0 : from, hi = j0 + kWave < e ? j0 + kWave : e;
+                    const uint64_t sec = request_bytes(lo, hi, sizeof(ColT), 32) / 32;
+                    t.isect += sec;
+                    t.reqb += 32 * sec;
+                }
+            }
+        }
+        if (hit && lane == 0) {
+            s.level[x] = s.tag;
+            atomicOr(&s.visited[x >> 5], 1u << (x & 31u));
+            atomicOr(&s.nextbits[x >> 5], 1u << (x & 31u));
+            nfound += 1;
+            fedges += e - b;
+        }
+    }
+    flush_tally(t, s.ctr);
+    add_counter(s.ctr, C_NEXT, nfound);
+    add_counter(s.ctr, C_FEDGES, fedges);
 }
 
 // ---------------------------------------------------------------------------
@@ -632,14 +881,14 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull(ScanArgs s, PrArgs pa) {
     constexpr int U = kGroupChunks<ColT>;
     const int lane = lane_id();
     OpArgs a{};  // the cursor reads only source_value<A_LINK>, which is the vertex id
-    uint64_t edges = 0, reqb = 0, verts = 0, tedges = 0, pkb = 0;
+    Tally t;
     ChunkCursor<ColT> c;
     c.total = s.chunk_scan[s.n];
     c.stride = uint64_t(gridDim.x) * kWavesPerBlock * kChunksPerWave;
     open_run<ColT, A_LINK>(c, s, a, (uint64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave) * kChunksPerWave);
     while (c.kb < c.kend) {
         ChunkGroup<U> g;
-        load_group<ColT, A_LINK>(c, g, s, a, lane, edges, reqb, verts, tedges, pkb);
+        load_group<ColT, A_LINK>(c, g, s, a, lane, t);
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const uint64_t x = (g.ok[i] && g.v[i] < s.n) ? pa.contrib[g.v[i]] : 0ull;
@@ -647,18 +896,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull(ScanArgs s, PrArgs pa) {
             if (lane == 0 && sum) atomicAdd(&pa.acc[g.uv[i]], (unsigned long long)sum);
         }
     }
-    edges = wave_sum64(edges);
-    reqb = wave_sum64(reqb);
-    verts = wave_sum64(verts);
-    tedges = wave_sum64(tedges);
-    pkb = wave_sum64(pkb);
-    if (lane == 0) {
-        if (edges) atomicAdd(&pa.ctr[C_EDGES], (unsigned long long)edges);
-        if (reqb) atomicAdd(&pa.ctr[C_REQBYTES], (unsigned long long)reqb);
-        if (verts) atomicAdd(&pa.ctr[C_VERTS], (unsigned long long)verts);
-        if (tedges) atomicAdd(&pa.ctr[C_TIER], (unsigned long long)tedges);
-        if (pkb) atomicAdd(&pa.ctr[C_PKBYTES], (unsigned long long)pkb);
-    }
+    flush_tally(t, pa.ctr);
 }
 
 // pr(v) = base + floor(d * acc(v) / 2^F); acc(v) = 0; c(v) = floor(pr(v) / deg(v)).
@@ -896,7 +1134,7 @@ constexpr int kCcProbe = 1024;
 template <class ColT>
 __global__ __launch_bounds__(kBlock) void k_cc_sample(const uint64_t *row_ptr, const ColT *col, uint64_t V,
                                                       TierView tier, uint32_t *parent, unsigned long long *ctr) {
-    uint64_t edges = 0, tedges = 0;
+    Tally t;
     for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
          v += uint64_t(gridDim.x) * blockDim.x) {
         const uint64_t b = row_ptr[v], e = row_ptr[v + 1];
@@ -907,13 +1145,17 @@ __global__ __launch_bounds__(kBlock) void k_cc_sample(const uint64_t *row_ptr, c
         for (uint64_t r = 0; r < n; ++r) nb[r] = src.col[b + r - src.shift];
         for (uint64_t r = 0; r < n; ++r)
             if (uint64_t(nb[r]) < V) uf_link(parent, uint32_t(v), uint32_t(nb[r]));
-        edges += n;
-        if (src.tier) tedges += n;
+        t.edges += n;
+        if (src.tier) {
+            t.tedges += n;
+        } else {
+            // a prefix read is its own short request: whole sectors
+            const uint64_t sec = request_bytes(b, b + n, sizeof(ColT), 32) / 32;
+            t.isect += sec;
+            t.reqb += 32 * sec;
+        }
     }
-    edges = wave_sum64(edges);
-    tedges = wave_sum64(tedges);
-    if (lane_id() == 0 && edges) atomicAdd(&ctr[C_EDGES], (unsigned long long)edges);
-    if (lane_id() == 0 && tedges) atomicAdd(&ctr[C_TIER], (unsigned long long)tedges);
+    flush_tally(t, ctr);
 }
 
 // Sampled hooking on packed lists: the first ids of block 0 of each list.
@@ -921,7 +1163,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_sample_packed(const uint64_t *row
                                                              const uint64_t *pk_off, const uint8_t *pk_width,
                                                              uint64_t V, uint32_t *parent,
                                                              unsigned long long *ctr) {
-    uint64_t edges = 0, pkb = 0;
+    uint64_t edges = 0, pkb = 0, isect = 0;
     for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
          v += uint64_t(gridDim.x) * blockDim.x) {
         const uint64_t d = row_ptr[v + 1] - row_ptr[v];
@@ -931,7 +1173,9 @@ __global__ __launch_bounds__(kBlock) void k_cc_sample_packed(const uint64_t *row
         const uint32_t w = pk_width[v];
         uint32_t x = pk[w0];
         if (x < V) uf_link(parent, uint32_t(v), x);
-        pkb += 4 + (n > 1 && w ? 4 * ((uint64_t(n - 1) * w + 31) / 32) : 0);
+        const uint64_t words = 1 + (n > 1 && w ? (uint64_t(n - 1) * w + 31) / 32 : 0);
+        pkb += 4 * words;
+        isect += request_bytes(w0, w0 + words, 4, 32) / 32;
         for (uint32_t r = 1; r < n; ++r) {
             const uint64_t o = uint64_t(r - 1) * w;
             const uint64_t wd = w0 + 1 + (o >> 5);
@@ -943,10 +1187,10 @@ __global__ __launch_bounds__(kBlock) void k_cc_sample_packed(const uint64_t *row
         }
         edges += n;
     }
-    edges = wave_sum64(edges);
-    pkb = wave_sum64(pkb);
-    if (lane_id() == 0 && edges) atomicAdd(&ctr[C_EDGES], (unsigned long long)edges);
-    if (lane_id() == 0 && pkb) atomicAdd(&ctr[C_PKBYTES], (unsigned long long)pkb);
+    add_counter(ctr, C_EDGES, edges);
+    add_counter(ctr, C_PKBYTES, pkb);
+    add_counter(ctr, C_IDSECT, isect);
+    add_counter(ctr, C_REQBYTES, 32 * isect);
 }
 
 __global__ void k_compress(uint32_t *parent, uint64_t V) {
@@ -992,12 +1236,47 @@ __global__ void k_overflow_check(const uint32_t *dist, const uint32_t *marks, ui
             atomicOr(&ctr[C_OVERFLOW], 2ull);
 }
 
+// Size and degree sum of a frontier held as marks (C_NEXT, C_FEDGES).
+__global__ __launch_bounds__(kBlock) void k_marks_tally(const uint32_t *bits, uint64_t words, const uint64_t *row_ptr,
+                                                         unsigned long long *ctr) {
+    uint64_t cnt = 0, deg = 0;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < words;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t w = bits[i];
+        cnt += __popc(w);
+        while (w) {
+            const uint64_t v = i * 32 + uint64_t(__ffs(w) - 1);
+            w &= w - 1;
+            deg += row_ptr[v + 1] - row_ptr[v];
+        }
+    }
+    add_counter(ctr, C_NEXT, cnt);
+    add_counter(ctr, C_FEDGES, deg);
+}
+
+// Sum of the out-degrees of the vertices with a finite value (C_FEDGES).
+__global__ __launch_bounds__(kBlock) void k_reached_edges(const uint32_t *state, const uint64_t *row_ptr, uint64_t V,
+                                                           unsigned long long *ctr) {
+    uint64_t deg = 0;
+    for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V; v += uint64_t(gridDim.x) * blockDim.x)
+        if (state[v] != 0xFFFFFFFFu) deg += row_ptr[v + 1] - row_ptr[v];
+    add_counter(ctr, C_FEDGES, deg);
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 static unsigned fill_grid(uint64_t n) {
     uint64_t g = (n + kBlock - 1) / kBlock;
     return unsigned(std::max<uint64_t>(1, std::min<uint64_t>(g, 4096)));
+}
+
+// Clears device words with a kernel (every buffer cleared here is whole
+// 32-bit words); errors surface at the caller's next launch check.
+static void zero_async(void *ptr, size_t bytes, hipStream_t stream) {
+    const uint64_t words = bytes / 4;
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid(words)), dim3(kBlock), 0, stream, static_cast<uint32_t *>(ptr), words,
+                       0u);
 }
 
 static emogi_status_t ensure_pool(emogi_graph_s *g, int algo) {
@@ -1116,6 +1395,31 @@ static uint32_t level_batch(const emogi_graph_s *g) {
     return g->E < (uint64_t(1) << 24) ? 8u : 1u;
 }
 
+// Whether BFS may run bottom-up levels (see emogi_set_direction): a vertex's
+// list must also list its incoming edges (symmetric graphs), and the
+// direction is picked per level on the host from the ordered frontier.
+static bool direction_allowed(const emogi_graph_s *g) {
+    return g->direction != EMOGI_DIR_TOP_DOWN && (g->flags & EMOGI_F_SYMMETRIC) && g->ordered_frontier &&
+           !g->packed.stream && g->sched_mode != EMOGI_SCHED_PROBE && g->V > 0 && level_batch(g) == 1;
+}
+
+// Direction of the next level (true: bottom-up), from the level just run
+// (bottom-up or not, its frontier size n) and the next frontier (n_next
+// vertices whose lists hold m_next edges); `explored` is the degree sum of
+// every vertex reached so far.  Beamer, Asanovic and Patterson (SC 2012):
+// go bottom-up when the next frontier's edges exceed the edges still
+// unexplored / alpha while the frontier grows; come back when it shrinks
+// below (vertices with edges) / beta.
+static bool choose_bottom_up(const emogi_graph_s *g, bool bu, uint64_t n, uint64_t n_next, uint64_t m_next,
+                             uint64_t explored) {
+    if (g->direction == EMOGI_DIR_BOTTOM_UP) return true;
+    if (!bu) {
+        const uint64_t unexplored = g->E > explored ? g->E - explored : 0;
+        return n_next > n && m_next * uint64_t(g->dir_alpha) > unexplored;
+    }
+    return !(n_next < n && n_next * uint64_t(g->dir_beta) < g->nonisolated);
+}
+
 static emogi_status_t ensure_level_blocks(emogi_graph_s *g, uint32_t lb) {
     Pool &p = g->pool;
     if (p.level_ctr && p.level_cap >= lb) return EMOGI_OK;
@@ -1143,11 +1447,12 @@ int heuristic_variant(const emogi_graph_s *g, uint64_t n) {
 }
 
 int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue, hipStream_t stream,
-                   float *features);
+                   float *features, int *by_network);
 emogi_status_t sched_begin(emogi_graph_s *g, hipStream_t stream);
 emogi_status_t sched_prefetch(emogi_graph_s *g, int algo, const uint32_t *queue, unsigned long long *counters,
                               hipStream_t stream);
-int choose_prefetched(const emogi_graph_s *g, uint64_t n, const unsigned long long *hc, float *features);
+int choose_prefetched(const emogi_graph_s *g, uint64_t n, const unsigned long long *hc, float *features,
+                      int *by_network);
 
 // Probe mode: save (restore=false) or restore (restore=true) the state a
 // level step modifies, so every variant can be timed on the same level.
@@ -1182,6 +1487,17 @@ static emogi_status_t snapshot(emogi_graph_s *g, int algo, uint32_t *out, hipStr
         EMOGI_HIP_TRY(cp(p.farbits, p.snap_farbits, words * 4), EMOGI_E_HIP);
     }
     return EMOGI_OK;
+}
+
+// Adds a level's (or a pass's) device counters to the traversal statistics.
+static void absorb_counters(emogi_stats_t &S, const unsigned long long *hc) {
+    S.edges_scanned += hc[C_EDGES];
+    S.tier_edges += hc[C_TIER];
+    S.request_bytes += hc[C_REQBYTES];
+    S.vertices_expanded += hc[C_VERTS];
+    S.weights_read += hc[C_WLINK];
+    S.id_sector_bytes += 32 * hc[C_IDSECT];
+    S.weight_sector_bytes += 32 * hc[C_WSECT];
 }
 
 static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_t *out,
@@ -1230,8 +1546,11 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             // sampled union-find: hook, compress, find the large tree, then one
             // full pass over the lists of the vertices outside it
             hipLaunchKernelGGL(k_iota, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
-            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
-                          EMOGI_E_HIP);
+            zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
+            // the sampling pass reads lists over the link like a level does:
+            // its time counts in expand_ms (its chunk prefix in prep_ms)
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_s0, stream), EMOGI_E_HIP);
+            bool sample_prefix = false;  // ev_k0 recorded between the prefix and the hooking scan
             const uint64_t davg = std::max<uint64_t>(1, g->E / V);
             if (g->max_degree <= 4 * davg) {
                 // Lists of about equal length (no hubs): a read of each list's
@@ -1268,6 +1587,8 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                     hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, stream, s, p.block_sums,
                                        p.chunk_scan);
                     s.chunk_scan = p.chunk_scan;
+                    EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
+                    sample_prefix = true;
                     OpArgs a{};
                     a.state = out;
                     a.V = uint32_t(V);
@@ -1291,6 +1612,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                                    static_cast<const uint32_t *>(g->col), V, tier_view(g), out, p.counters);
             }
             EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
             hipLaunchKernelGGL(k_compress, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
             hipLaunchKernelGGL(k_cc_probe, dim3((kCcProbe + 255) / 256), dim3(256), 0, stream, out, V,
                                p.cc_probe);
@@ -1302,8 +1624,15 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                                          hipMemcpyDeviceToHost, stream),
                           EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
-            S.edges_scanned += p.host_counters[C_EDGES];
-            S.tier_edges += p.host_counters[C_TIER];
+            {
+                float total_ms = 0.f, prep = 0.f;
+                EMOGI_HIP_TRY(hipEventElapsedTime(&total_ms, g->ev_s0, g->ev_k1), EMOGI_E_HIP);
+                if (sample_prefix) EMOGI_HIP_TRY(hipEventElapsedTime(&prep, g->ev_s0, g->ev_k0), EMOGI_E_HIP);
+                S.expand_ms += total_ms;
+                S.prep_ms += prep;
+                S.expand_launches += 1;
+            }
+            absorb_counters(S, p.host_counters);
             packed_bytes += p.host_counters[C_PKBYTES];
             std::sort(roots.begin(), roots.end());
             uint32_t big = roots[0], best = 0;
@@ -1314,8 +1643,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                     big = roots[i];
                 }
             }
-            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
-                          EMOGI_E_HIP);
+            zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
             hipLaunchKernelGGL(k_cc_outside, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, g->row_ptr, V, big,
                                p.queue[0], p.counters);
             EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
@@ -1326,13 +1654,12 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             kalgo = A_LINK;
         } else if (algo == A_CC) {
             hipLaunchKernelGGL(k_iota, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V);
-            EMOGI_HIP_TRY(hipMemsetAsync(p.stamp, 0, V * sizeof(uint32_t), stream), EMOGI_E_HIP);
+            zero_async(p.stamp, V * sizeof(uint32_t), stream);
             n = V;
             identity = true;  // every vertex starts active (Sec. 5.4)
         } else {
             hipLaunchKernelGGL(k_fill, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V, 0xFFFFFFFFu);
-            EMOGI_HIP_TRY(hipMemsetAsync(p.bitmap, 0, ((V + 31) / 32) * sizeof(uint32_t), stream),
-                          EMOGI_E_HIP);
+            zero_async(p.bitmap, ((V + 31) / 32) * sizeof(uint32_t), stream);
             hipLaunchKernelGGL(k_seed_source, dim3(1), dim3(64), 0, stream, out, p.bitmap, p.queue[0],
                                uint32_t(src), algo == A_BFS ? 1 : 0);
             n = 1;
@@ -1364,7 +1691,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             set_error("hipMalloc of the ordered-frontier bitmap failed");
             return EMOGI_E_OOM_DEVICE;
         }
-        EMOGI_HIP_TRY(hipMemsetAsync(p.nextbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
+        zero_async(p.nextbits, ((V + 31) / 32) * sizeof(uint32_t), stream);
         if (algo == A_SSSP) {
             if (!p.farbits && hipMalloc(&p.farbits, ((V + 31) / 32) * sizeof(uint32_t)) != hipSuccess) {
                 (void)hipGetLastError();
@@ -1372,7 +1699,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 set_error("hipMalloc of the SSSP band bitmap failed");
                 return EMOGI_E_OOM_DEVICE;
             }
-            EMOGI_HIP_TRY(hipMemsetAsync(p.farbits, 0, ((V + 31) / 32) * sizeof(uint32_t), stream), EMOGI_E_HIP);
+            zero_async(p.farbits, ((V + 31) / 32) * sizeof(uint32_t), stream);
         }
     }
     // SSSP distance bands (Sec. 5.1 leaves the SSSP algorithm open; this is a
@@ -1407,7 +1734,8 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     // The scheduler's features and pick for the next frontier are computed
     // behind each level and come back with its counters (have_pick); the
     // first frontier, and one opened by an SSSP band step, is scored on its own.
-    const bool prefetch = V > 0 && sched_needs_features(g);
+    // (BFS with bottom-up levels scores each top-down frontier on its own)
+    const bool prefetch = V > 0 && sched_needs_features(g) && !(algo == A_BFS && direction_allowed(g));
     bool have_pick = false;
     if (prefetch && (st = sched_begin(g, stream)) != EMOGI_OK) return st;
 
@@ -1435,8 +1763,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 return EMOGI_E_NOCONVERGE;
             }
             const uint32_t k = uint32_t(std::min<uint64_t>(lb, cap - iter));  // the cap holds exactly
-            EMOGI_HIP_TRY(hipMemsetAsync(p.level_ctr, 0, size_t(k) * C_COUNT * sizeof(unsigned long long), stream),
-                          EMOGI_E_HIP);
+            zero_async(p.level_ctr, size_t(k) * C_COUNT * sizeof(unsigned long long), stream);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
             for (uint32_t i = 0; i < k; ++i) {
                 ScanArgs s;
@@ -1497,10 +1824,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 }
                 S.variant_hist[var] += 1;
                 S.expand_launches += 1;
-                S.edges_scanned += hc[C_EDGES];
-                S.tier_edges += hc[C_TIER];
-                S.request_bytes += hc[C_REQBYTES];
-                S.vertices_expanded += hc[C_VERTS];
+                absorb_counters(S, hc);
                 n = hc[C_NEXT];
                 ++iter;
             }
@@ -1509,6 +1833,24 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 if (iter - ran + i < EMOGI_MAX_LEVEL_STATS) S.level_ms[iter - ran + i] = ms / float(ran);
         }
     }
+    // Direction-optimizing BFS (emogi_set_direction): `bu` says the current
+    // frontier is held as the bitmap fbits and the level runs bottom-up.
+    // The next frontier is always collected as marks (nextbits); after each
+    // level one pass counts them and sums their degrees, the host picks the
+    // next level's direction, and the marks are either listed into the queue
+    // (top-down) or become the frontier bitmap (bottom-up).
+    const bool do_bfs = algo == A_BFS && ordered && direction_allowed(g);
+    if (do_bfs && !p.fbits) {
+        if (hipMalloc(&p.fbits, words * sizeof(uint32_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            p.fbits = nullptr;
+            set_error("hipMalloc of the bottom-up frontier bitmap failed");
+            return EMOGI_E_OOM_DEVICE;
+        }
+    }
+    bool bu = false;
+    uint64_t explored = 0;  // degree sum of the vertices reached so far
+    const int colkind = g->col_bytes == 8 ? 1 : 0;
     while (true) {
         if (n == 0) {
             // SSSP: the band is exhausted; open the next one at the smallest
@@ -1516,7 +1858,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             // minimum), or stop when nothing waits
             have_pick = false;
             if (algo != A_SSSP || split == 0xFFFFFFFFu) break;
-            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
+            zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
             hipLaunchKernelGGL(k_bits_count, dim3(nbw), dim3(kBlock), 0, stream, p.farbits, words, out, 0u,
                                p.block_sums, p.counters);
             if ((st = sync_counters()) != EMOGI_OK) return st;
@@ -1524,7 +1866,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             if (bm == 0) break;
             const uint64_t m = 0x100000000ull - bm;
             split = uint32_t(std::min<uint64_t>(std::max<uint64_t>(m + delta, split), 0xFFFFFFFFull));
-            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
+            zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
             list_marks(p.farbits, out, split, p.queue[cur], nullptr);
             if ((st = sync_counters()) != EMOGI_OK) return st;
             n = p.host_counters[C_NEXT];
@@ -1536,9 +1878,11 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             return EMOGI_E_NOCONVERGE;
         }
         const uint32_t *queue = identity ? nullptr : p.queue[cur];
-        // One level with variant `v`: counters cleared, (V5) chunk scan, the
-        // scan kernel between two events, counters copied back, host waits.
-        auto run_level = [&](int v, float *ms_out) -> emogi_status_t {
+        // One level with variant `v`: counters cleared, (V5) chunk prefix
+        // between ev_s0 and ev_k0, the scan kernel between ev_k0 and ev_k1,
+        // counters copied back, host waits.  *ms_out: the scan kernel,
+        // *prep_out: the prefix.
+        auto run_level = [&](int v, float *ms_out, float *prep_out) -> emogi_status_t {
             ScanArgs s;
             s.queue = queue;
             s.n = uint32_t(n);
@@ -1565,8 +1909,8 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             a.farbits = p.farbits;
             a.wmin = g->min_weight;
             a.inmin = g->in_min;
-            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
-                          EMOGI_E_HIP);
+            zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_s0, stream), EMOGI_E_HIP);
             if (v == EMOGI_V5_BALANCED) {
                 emogi_status_t e2 = ensure_scan(g, n);
                 if (e2 != EMOGI_OK) return e2;
@@ -1578,7 +1922,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 s.chunk_scan = p.chunk_scan;
             }
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
-            const int key = g->packed.stream ? 8 + kalgo : kalgo * 2 + (g->col_bytes == 8 ? 1 : 0);
+            const int key = g->packed.stream ? 8 + kalgo : kalgo * 2 + colkind;
             switch (key) {
             case 8 + A_BFS: launch_packed<A_BFS>(s, a, stream); break;
             case 8 + A_SSSP: launch_packed<A_SSSP>(s, a, stream); break;
@@ -1595,7 +1939,7 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             }
             EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
-            if (ordered) {
+            if (ordered && !do_bfs) {
                 list_marks(p.nextbits, nullptr, 0xFFFFFFFFu, s.next, algo == A_SSSP ? p.farbits : nullptr);
                 EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             }
@@ -1608,55 +1952,127 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                           EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipEventElapsedTime(ms_out, g->ev_k0, g->ev_k1), EMOGI_E_HIP);
+            *prep_out = 0.f;
+            if (v == EMOGI_V5_BALANCED) EMOGI_HIP_TRY(hipEventElapsedTime(prep_out, g->ev_s0, g->ev_k0), EMOGI_E_HIP);
             return EMOGI_OK;
         };
-        float feats[16];
-        const bool want_feats = g->record_features && iter < EMOGI_MAX_LEVEL_STATS;
-        int var = have_pick ? choose_prefetched(g, n, p.host_counters, want_feats ? feats : nullptr)
-                            : choose_variant(g, algo, n, queue, stream, want_feats ? feats : nullptr);
-        if (var < 0) {
-            set_error("scheduler kernels failed");
-            return EMOGI_E_HIP;
-        }
-        if (want_feats) memcpy(S.level_features[iter], feats, sizeof(feats));
-        if (g->packed.stream) var = EMOGI_V5_BALANCED;  // the one variant that decodes packed lists
-        if (g->sched_mode == EMOGI_SCHED_PROBE && !g->packed.stream) {
-            // Time every variant on the same level state, then run the fastest.
-            if ((st = snapshot(g, algo, out, stream, false)) != EMOGI_OK) return st;
-            float best = 1e30f;
-            for (int v = 0; v < EMOGI_NUM_VARIANTS; ++v) {
-                if (v > 0 && (st = snapshot(g, algo, out, stream, true)) != EMOGI_OK) return st;
-                float pm = 0.f;
-                if ((st = run_level(v, &pm)) != EMOGI_OK) return st;
-                if (iter < EMOGI_MAX_LEVEL_STATS) S.level_probe_ms[iter][v] = pm;
-                if (pm < best) {
-                    best = pm;
-                    var = v;
-                }
+        // One bottom-up level: the probe over every vertex tile, then a wave
+        // per vertex the probe left; *ms_out: both kernels.
+        auto run_bottom_up = [&](float *ms_out) -> emogi_status_t {
+            BuArgs b;
+            b.row_ptr = g->row_ptr;
+            b.col = g->col;
+            b.tier = tier_view(g);
+            b.V = V;
+            b.fbits = p.fbits;
+            b.visited = p.bitmap;
+            b.nextbits = p.nextbits;
+            b.level = out;
+            b.tag = iter + 1;
+            b.rest = p.queue[cur ^ 1];
+            b.ctr = p.counters;
+            zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
+            const uint64_t tiles = (V + 63) / 64;
+            const unsigned grid = unsigned(std::max<uint64_t>(
+                1, std::min<uint64_t>((tiles + kWavesPerBlock - 1) / kWavesPerBlock, kMaxGrid)));
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
+            if (colkind) {
+                hipLaunchKernelGGL(k_bu_probe<uint64_t>, dim3(grid), dim3(kBlock), 0, stream, b);
+                hipLaunchKernelGGL(k_bu_rest<uint64_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, b);
+            } else {
+                hipLaunchKernelGGL(k_bu_probe<uint32_t>, dim3(grid), dim3(kBlock), 0, stream, b);
+                hipLaunchKernelGGL(k_bu_rest<uint32_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, b);
             }
-            if ((st = snapshot(g, algo, out, stream, true)) != EMOGI_OK) return st;
+            EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+            EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
+            if ((st = sync_counters()) != EMOGI_OK) return st;
+            EMOGI_HIP_TRY(hipEventElapsedTime(ms_out, g->ev_k0, g->ev_k1), EMOGI_E_HIP);
+            return EMOGI_OK;
+        };
+        float ms = 0.f, prep = 0.f;
+        int var = 0;
+        if (bu) {
+            if ((st = run_bottom_up(&ms)) != EMOGI_OK) return st;
+            S.bottom_up_levels += 1;
+        } else {
+            float feats[16];
+            const bool want_feats = g->record_features && iter < EMOGI_MAX_LEVEL_STATS;
+            int by_net = 0;
+            var = have_pick ? choose_prefetched(g, n, p.host_counters, want_feats ? feats : nullptr, &by_net)
+                            : choose_variant(g, algo, n, queue, stream, want_feats ? feats : nullptr, &by_net);
+            if (var < 0) {
+                set_error("scheduler kernels failed");
+                return EMOGI_E_HIP;
+            }
+            if (want_feats) memcpy(S.level_features[iter], feats, sizeof(feats));
+            if (g->packed.stream) {
+                var = EMOGI_V5_BALANCED;  // the one variant that decodes packed lists
+                by_net = 0;
+            }
+            if (g->sched_mode == EMOGI_SCHED_PROBE && !g->packed.stream) {
+                // Time every variant on the same level state (its preparation
+                // kernels included), then run the fastest.
+                if ((st = snapshot(g, algo, out, stream, false)) != EMOGI_OK) return st;
+                float best = 1e30f;
+                for (int v = 0; v < EMOGI_NUM_VARIANTS; ++v) {
+                    if (v > 0 && (st = snapshot(g, algo, out, stream, true)) != EMOGI_OK) return st;
+                    float pm = 0.f, pp = 0.f;
+                    if ((st = run_level(v, &pm, &pp)) != EMOGI_OK) return st;
+                    if (iter < EMOGI_MAX_LEVEL_STATS) S.level_probe_ms[iter][v] = pm + pp;
+                    if (pm + pp < best) {
+                        best = pm + pp;
+                        var = v;
+                    }
+                }
+                if ((st = snapshot(g, algo, out, stream, true)) != EMOGI_OK) return st;
+            }
+            if ((st = run_level(var, &ms, &prep)) != EMOGI_OK) return st;
+            have_pick = prefetch;
+            S.variant_hist[var] += 1;
+            S.levels_by_network += by_net ? 1 : 0;
         }
-        float ms = 0.f;
-        if ((st = run_level(var, &ms)) != EMOGI_OK) return st;
-        have_pick = prefetch;
         const unsigned long long *hc = p.host_counters;
         if (iter < EMOGI_MAX_LEVEL_STATS) {
-            S.level_variant[iter] = uint8_t(var);
+            S.level_variant[iter] = bu ? uint8_t(EMOGI_NUM_VARIANTS) : uint8_t(var);
+            S.level_direction[iter] = bu ? 1 : 0;
             S.level_frontier[iter] = uint32_t(n);
             S.level_ms[iter] = ms;
             S.level_edges[iter] = hc[C_EDGES];
             S.level_count = iter + 1;
         }
-        S.variant_hist[var] += 1;
-        S.expand_ms += ms;
+        S.expand_ms += ms + prep;
+        S.prep_ms += prep;
         S.expand_launches += 1;
-        S.edges_scanned += hc[C_EDGES];
-        S.tier_edges += hc[C_TIER];
-        S.request_bytes += hc[C_REQBYTES];
-        S.vertices_expanded += hc[C_VERTS];
-        S.weights_read += hc[C_WLINK];
+        absorb_counters(S, hc);
         packed_bytes += hc[C_PKBYTES];
         if (hc[C_OVERFLOW]) overflow_seen = true;
+        if (do_bfs) {
+            if (iter == 0) explored = hc[C_EDGES];  // the source's list (a top-down level)
+            uint64_t n_next = hc[C_NEXT], m_next = hc[C_FEDGES];
+            if (!bu) {
+                // a top-down level left marks only: count them, sum their degrees
+                zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
+                hipLaunchKernelGGL(k_marks_tally, dim3(fill_grid(words)), dim3(kBlock), 0, stream, p.nextbits, words,
+                                   g->row_ptr, p.counters);
+                if ((st = sync_counters()) != EMOGI_OK) return st;
+                n_next = p.host_counters[C_NEXT];
+                m_next = p.host_counters[C_FEDGES];
+            }
+            explored += m_next;
+            const bool next_bu = n_next > 0 && choose_bottom_up(g, bu, n, n_next, m_next, explored);
+            if (next_bu) {
+                std::swap(p.fbits, p.nextbits);
+                zero_async(p.nextbits, words * sizeof(uint32_t), stream);
+            } else if (n_next > 0) {
+                list_marks(p.nextbits, nullptr, 0xFFFFFFFFu, p.queue[cur ^ 1], nullptr);
+                EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+            }
+            n = n_next;
+            bu = next_bu;
+            cur ^= 1;
+            ++iter;
+            continue;
+        }
         n = hc[C_NEXT];
         if (identity) {
             identity = false;
@@ -1673,9 +2089,22 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     // SSSP weights only where read
     S.useful_link_bytes = (g->packed.stream ? packed_bytes : (S.edges_scanned - S.tier_edges) * g->col_bytes) +
                           S.weights_read * 4;
+    // the TEPS numerator: a top-down BFS expands every reached vertex once;
+    // bottom-up levels sum the found vertices' degrees instead; SSSP adds up
+    // the reached vertices' degrees in one pass; CC counts every edge
+    if (algo == A_BFS) {
+        S.reached_edges = do_bfs ? explored : S.edges_scanned;
+    } else if (algo == A_SSSP && V > 0) {
+        zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
+        hipLaunchKernelGGL(k_reached_edges, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, g->row_ptr, V,
+                           p.counters);
+        if ((st = sync_counters()) != EMOGI_OK) return st;
+        S.reached_edges = p.host_counters[C_FEDGES];
+    } else if (algo == A_CC) {
+        S.reached_edges = g->E;
+    }
     if (overflow_seen) {
-        EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream),
-                      EMOGI_E_HIP);
+        zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
         hipLaunchKernelGGL(k_overflow_check, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, p.bitmap,
                            V, p.counters);
         EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),
@@ -1758,7 +2187,7 @@ static emogi_status_t pagerank(emogi_graph_s *g, uint32_t iters, uint32_t F, uin
         EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
         PrArgs pa{p.pr_contrib, p.pr_acc, p.counters};
         for (uint32_t t = 0; t < iters; ++t) {
-            EMOGI_HIP_TRY(hipMemsetAsync(p.counters, 0, C_COUNT * sizeof(unsigned long long), stream), EMOGI_E_HIP);
+            zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
             if (g->packed.stream)
                 hipLaunchKernelGGL(k_pr_pull<PackedCol>, dim3(kMaxGrid), dim3(kBlock), 0, stream, s, pa);
@@ -1787,14 +2216,12 @@ static emogi_status_t pagerank(emogi_graph_s *g, uint32_t iters, uint32_t F, uin
             S.variant_hist[EMOGI_V5_BALANCED] += 1;
             S.expand_ms += ms;
             S.expand_launches += 1;
-            S.edges_scanned += hc[C_EDGES];
-            S.tier_edges += hc[C_TIER];
-            S.request_bytes += hc[C_REQBYTES];
-            S.vertices_expanded += hc[C_VERTS];
+            absorb_counters(S, hc);
             packed_bytes += hc[C_PKBYTES];
         }
     }
     S.iterations = iters;
+    S.reached_edges = g->E;
     S.useful_link_bytes = g->packed.stream ? packed_bytes : (S.edges_scanned - S.tier_edges) * g->col_bytes;
     EMOGI_HIP_TRY(hipEventRecord(g->ev_end, stream), EMOGI_E_HIP);
     EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);

@@ -54,6 +54,13 @@ class Stats(ctypes.Structure):
         ("level_edges", ctypes.c_uint64 * MAX_LEVEL_STATS),
         ("level_features", (ctypes.c_float * 16) * MAX_LEVEL_STATS),
         ("level_probe_ms", (ctypes.c_float * 6) * MAX_LEVEL_STATS),
+        ("prep_ms", ctypes.c_double),
+        ("reached_edges", ctypes.c_uint64),
+        ("id_sector_bytes", ctypes.c_uint64),
+        ("weight_sector_bytes", ctypes.c_uint64),
+        ("levels_by_network", ctypes.c_uint32),
+        ("bottom_up_levels", ctypes.c_uint32),
+        ("level_direction", ctypes.c_uint8 * MAX_LEVEL_STATS),
     ]
 
     def as_dict(self):
@@ -77,6 +84,13 @@ class Stats(ctypes.Structure):
             "level_edges": list(self.level_edges[:n]),
             "level_features": [list(self.level_features[i]) for i in range(n)],
             "level_probe_ms": [list(self.level_probe_ms[i]) for i in range(n)],
+            "prep_ms": self.prep_ms,
+            "reached_edges": self.reached_edges,
+            "id_sector_bytes": self.id_sector_bytes,
+            "weight_sector_bytes": self.weight_sector_bytes,
+            "levels_by_network": self.levels_by_network,
+            "bottom_up_levels": self.bottom_up_levels,
+            "level_direction": list(self.level_direction[:n]),
         }
 
 
@@ -196,6 +210,8 @@ def lib():
             "emogi_set_hbm_tier": (i32, [p, u64, p, p]),
             "emogi_set_level_batch": (i32, [p, u32]),
             "emogi_set_frontier_order": (i32, [p, i32]),
+            "emogi_set_direction": (i32, [p, i32, u32, u32]),
+            "emogi_graph_setup_ms": (i32, [p, ctypes.POINTER(ctypes.c_double)]),
             "emogi_set_scheduler_weights": (i32, [p, p, sz]),
             "emogi_set_scheduler_range": (i32, [p, p, p]),
             "emogi_bfs": (i32, [p, u64, p, p]),
@@ -363,6 +379,19 @@ class Graph:
     def set_frontier_order(self, ordered):
         """True: list each next frontier in ascending vertex id (bitmap compaction)."""
         check(lib().emogi_set_frontier_order(self._h, int(bool(ordered))))
+
+    def set_direction(self, mode, alpha=0, beta=0):
+        """BFS level direction: 'top_down', 'auto' (default) or 'bottom_up';
+        alpha/beta of the switching rule (0 keeps the current values)."""
+        m = {"top_down": 0, "auto": 1, "bottom_up": 2}[mode]
+        check(lib().emogi_set_direction(self._h, m, int(alpha), int(beta)))
+
+    def setup_ms(self):
+        """Milliseconds of the create-time pass that found each vertex's
+        smallest incoming weight (0 when it did not run)."""
+        x = ctypes.c_double(0)
+        check(lib().emogi_graph_setup_ms(self._h, ctypes.byref(x)))
+        return x.value
 
     def set_cc_algorithm(self, name):
         """'label_propagation' or 'sampled_union_find' (default)."""
