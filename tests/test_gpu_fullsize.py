@@ -2,7 +2,10 @@
 
 * R-MAT scale 27 (edgefactor 16, ~4.2 billion directed edges), uint64
   neighbour ids and uint32 weights in pinned host memory read in place,
-  heuristic scheduler, 256-byte request unit.  BFS levels and CC labels are
+  heuristic scheduler, 256-byte request unit; BFS with its default
+  per-level direction and all top-down; then the same pinned arrays as
+  packed lists (gaps of up to 27 bits, every packed launch wrapping its
+  grid).  BFS levels and CC labels are
   compared with the oracle element by element; SSSP distances (Dijkstra on 4
   billion edges is too slow for a test) are checked with the oracle's exact
   linear-time certificate, which holds iff the vector equals the true
@@ -52,24 +55,44 @@ def test_fullsize_kron27_u64_zero_copy(gpu_device):
         G.set_scheduler("heuristic")
         G.bfs(src, out)
         lv = E.to_u32(out)
+        dirs = G.stats()["level_direction"]
+        G.set_direction("top_down")
+        G.bfs(src, out)
+        lv_td = E.to_u32(out)
+        G.set_direction("auto")
         G.sssp(src, out)
         dist = E.to_u32(out)
         G.cc(out)
         lab = E.to_u32(out)
-    say("GPU traversals done; running the oracle")
+    say(f"GPU traversals done (BFS level directions {dirs}); packed lists next")
+    # the packed arm of the benchmark: the same pinned arrays, bit-packed per list
+    with E.Graph(rp, col, w, symmetric=True, borrow=True, pack=True) as P:
+        P.bfs(src, out)
+        p_lv = E.to_u32(out)
+        p_edges = max(P.stats()["level_edges"])
+        P.sssp(src, out)
+        p_dist = E.to_u32(out)
+        P.cc(out)
+        p_lab = E.to_u32(out)
+    assert p_edges > 65536 * 64, "no packed BFS level wraps the edge-balanced grid"
+    say("packed traversals done; running the oracle")
     t = time.time()
     ref = oracle.bfs(rp, col.array, src)
     assert np.array_equal(lv, ref), "BFS levels differ from the oracle"
-    say(f"BFS equal ({time.time() - t:.0f}s)")
+    assert np.array_equal(lv_td, ref), "top-down BFS levels differ from the oracle"
+    assert np.array_equal(p_lv, ref), "packed BFS levels differ from the oracle"
+    say(f"BFS equal: direction-optimizing, top-down, packed ({time.time() - t:.0f}s)")
     t = time.time()
     assert oracle.certify_distances(rp, col.array, src, dist, w.array) == 0, "SSSP certificate failed"
+    assert np.array_equal(p_dist, dist), "packed SSSP distances differ"
     # the reachable set is the same for any positive weights
     assert np.array_equal(dist == E.INF, ref == E.INF)
-    say(f"SSSP certified ({time.time() - t:.0f}s)")
+    say(f"SSSP certified, packed equal ({time.time() - t:.0f}s)")
     t = time.time()
     ref_cc = oracle.cc(rp, col.array)
     assert np.array_equal(lab, ref_cc), "CC labels differ from the oracle"
-    say(f"CC equal ({time.time() - t:.0f}s)")
+    assert np.array_equal(p_lab, ref_cc), "packed CC labels differ from the oracle"
+    say(f"CC equal, plain and packed ({time.time() - t:.0f}s)")
     col.free()
     w.free()
 

@@ -151,12 +151,14 @@ def test_packed_link_bytes(gpu_device):
             assert set(G.stats()["level_variant"]) == {5}, mode
 
 
-def test_packed_wide_gaps(gpu_device):
-    """Ids spread over 2^25 vertices: gap widths of 20-25 bits, so gaps
-    straddle words in every way; lists of 1, 63, 64, 65 and 300 ids."""
+@pytest.mark.parametrize("id_bits", [25, 28])
+def test_packed_wide_gaps(gpu_device, id_bits):
+    """Ids spread over 2^25 (2^28) vertices: gap widths of 20-25 (23-28)
+    bits, so gaps straddle words in every way (R-MAT scale 27 needs 26-27
+    bits); lists of 1, 63, 64, 65 and 300 ids."""
     import torch
     import paper_2006_06890_amd as E
-    V = (1 << 25) + 5
+    V = (1 << id_bits) + 5
     rng = np.random.Generator(np.random.PCG64(11))
     edges = []
     hubs = [0, 17, V - 1, 1 << 24]
