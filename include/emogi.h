@@ -64,6 +64,7 @@ typedef enum {
                                         alive and unmodified until emogi_graph_destroy */
 #define EMOGI_F_PIN_NONCOHERENT 0x8u /* pinned edge list allocated non-coherent */
 #define EMOGI_F_PACK 0x10u           /* store the lists compressed (see emogi_packed_bytes) */
+#define EMOGI_F_WEIGHT_BOUND 0x20u   /* compute weight bounds at creation (see emogi_graph_create) */
 
 /* Access variants of the neighbour scan (all give identical results). */
 typedef enum {
@@ -137,7 +138,9 @@ typedef struct {
 
 /* ---- host-link calibration (the MI355X counterpart of the paper's toy 1-D
  *      zero-copy copy study, Sec. 3.3 and Fig. 4) ---- */
-#define EMOGI_CALIB_BLOCKS 8 /* random-read block sizes 32, 64, ..., 4096 bytes */
+#define EMOGI_CALIB_BLOCKS 8  /* random-read block sizes 32, 64, ..., 4096 bytes */
+#define EMOGI_CALIB_WAVES 10  /* waves in flight 16, 32, ..., 8192 */
+#define EMOGI_CALIB_OFFSETS 17 /* block start offsets 0, s, 2s, ..., 16s with s = max(16, R/16) */
 typedef struct {
     double memcpy_GBps;        /* hipMemcpy pinned host -> device, best of 3 (Sec. 5.3.2's peak) */
     double seq_read_GBps[3];   /* wave-merged sequential kernel reads, 4/8/16-byte lanes        */
@@ -147,11 +150,31 @@ typedef struct {
     uint32_t request_unit;     /* R: smallest aligned block reaching 90% of the sequential rate  */
     double latency_us;         /* dependent-load round trip to pinned host memory                */
     uint64_t buffer_bytes;     /* size of the pinned buffer used                                 */
+    /* Little's law (Sec. 3.3): random aligned R-byte blocks read by a fixed
+     * number of waves, each with one block in flight at a time */
+    uint32_t waves[EMOGI_CALIB_WAVES];
+    double waves_GBps[EMOGI_CALIB_WAVES];
+    uint32_t knee_waves;       /* fewest waves reaching 90% of the sweep's best rate             */
+    /* Fig. 4 (b) vs (c): random R-byte blocks whose start lies `offset` bytes
+     * past an R boundary (each block then spans two request units unless 0 or R) */
+    uint32_t offset_bytes[EMOGI_CALIB_OFFSETS];
+    double offset_GBps[EMOGI_CALIB_OFFSETS];
+    /* the same buffer size pinned non-coherent (hipHostMallocNonCoherent) */
+    double nc_memcpy_GBps;
+    double nc_seq_read_GBps;   /* 16-byte lanes */
+    double nc_rand_GBps;       /* random aligned R-byte blocks */
+    double coh_rand_GBps;      /* the coherent buffer, same kernel and launch as nc_rand_GBps */
+    /* GPU memory (HBM) for the vertex state: a wave-merged read of a device
+     * buffer, and a device-to-device copy counted as read + write bytes */
+    double hbm_read_GBps;
+    double hbm_copy_GBps;
 } emogi_link_profile_t;
 
 /* Measures the host link with a pinned buffer of `bytes` (>= 64 MiB; a few GiB
- * recommended) on the current device and null stream.  Allocates and frees its
- * own memory.  EMOGI_E_OOM_* when the buffers cannot be allocated. */
+ * recommended) on the current device and null stream, and GPU memory with a
+ * device buffer of the same size.  Allocates and frees its own memory (two
+ * pinned buffers, coherent and non-coherent, and two device buffers).
+ * EMOGI_E_OOM_* when the buffers cannot be allocated. */
 emogi_status_t emogi_calibrate_link(size_t bytes, emogi_link_profile_t *out);
 
 /* ---- pinned host memory for EMOGI_F_BORROW (Sec. 3.1: the edge list must be
@@ -165,10 +188,16 @@ emogi_status_t emogi_host_free(void *p);
  * row_ptr     host uint64[num_vertices+1], row_ptr[0] == 0, non-decreasing;
  *             E = row_ptr[V].  Copied into GPU memory.
  * col         host array of E neighbour ids, col_bytes = 4 or 8, each < V.
- * weights     host uint32[E] edge weights (NULL: SSSP unavailable).  With
- *             weights in host zero-copy placement, creation reads the edge
- *             list once on the GPU to find each vertex's smallest incoming
- *             weight (V bytes of GPU memory).
+ * weights     host uint32[E] edge weights (NULL: SSSP unavailable).
+ *             By default creation reads no weight: the lists are mapped and
+ *             nothing is preprocessed.  With EMOGI_F_WEIGHT_BOUND it finds
+ *             the smallest weight (a host pass) and, in host zero-copy
+ *             placement, each vertex's smallest incoming weight (one GPU
+ *             pass over col and weights across the link, V bytes of GPU
+ *             memory; its time is reported by emogi_graph_setup_ms); SSSP
+ *             then skips the weight read of every edge that cannot improve
+ *             its target (dist(v) <= dist(u) + that bound).  Without the
+ *             bounds it skips those with dist(v) <= dist(u).
  * placement   where col and weights live (see emogi_placement_t).
  * Errors: EMOGI_E_INVALID (bad sizes, V >= 2^32-1, malformed CSR under
  * EMOGI_F_VALIDATE, BORROW of memory not from emogi_host_alloc),
@@ -384,8 +413,8 @@ emogi_status_t emogi_set_hbm_tier(emogi_graph_t g, uint64_t budget_bytes, uint64
 emogi_status_t emogi_set_direction(emogi_graph_t g, int mode, uint32_t alpha, uint32_t beta);
 
 /* Create-time passes of the graph: milliseconds spent computing each
- * vertex's smallest incoming weight (the SSSP weight-read bound; 0 when it
- * was not computed).  The pass reads col and weights once over the link. */
+ * vertex's smallest incoming weight (EMOGI_F_WEIGHT_BOUND's GPU pass; 0 when
+ * it was not computed).  The pass reads col and weights once over the link. */
 emogi_status_t emogi_graph_setup_ms(emogi_graph_t g, double *in_min_ms);
 
 /* Statistics of the last traversal on this handle. */

@@ -561,7 +561,7 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
     // The smallest weight bounds what an edge can add to a distance: SSSP
     // skips the weight read of an edge whose target is already that close.
     g->min_weight = 0;
-    if (weights && E > 0) {
+    if (weights && E > 0 && (flags & EMOGI_F_WEIGHT_BOUND)) {
         const unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
         std::vector<uint32_t> part(nt, 0xFFFFFFFFu);
         std::vector<std::thread> th;
@@ -601,7 +601,8 @@ emogi_status_t emogi_graph_create(const uint64_t *row_ptr, uint64_t V, const voi
         g->weights = static_cast<uint32_t *>(w);
         // the per-target bound pays only where a weight read crosses the
         // host link; from HBM the extra gather costs more than it saves
-        if (st == EMOGI_OK && E > 0 && placement == EMOGI_PLACE_HOST_ZERO_COPY) st = compute_in_min(g);
+        if (st == EMOGI_OK && E > 0 && placement == EMOGI_PLACE_HOST_ZERO_COPY && (flags & EMOGI_F_WEIGHT_BOUND))
+            st = compute_in_min(g);
     }
     if (st == EMOGI_OK) {
         for (hipEvent_t *e : {&g->ev_begin, &g->ev_end, &g->ev_k0, &g->ev_k1, &g->ev_s0})

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libemogi.so")
 
 PLACEMENTS = {"hbm": 0, "host_zero_copy": 1, "managed": 2}
-F_SYMMETRIC, F_VALIDATE, F_BORROW, F_PIN_NONCOHERENT, F_PACK = 0x1, 0x2, 0x4, 0x8, 0x10
+F_SYMMETRIC, F_VALIDATE, F_BORROW, F_PIN_NONCOHERENT, F_PACK, F_WEIGHT_BOUND = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 SCHED_HEURISTIC, SCHED_LEARNED, SCHED_PROBE, SCHED_RECORD = 16, 17, 18, 0x100
 VARIANTS = ["V0_thread", "V1_group16", "V2_wave", "V3_wave_aligned", "V4_block", "V5_balanced"]
 N_SCHED_PARAMS = 5638
@@ -95,6 +95,8 @@ class Stats(ctypes.Structure):
 
 
 CALIB_BLOCKS = 8
+CALIB_WAVES = 10
+CALIB_OFFSETS = 17
 
 
 class LinkProfile(ctypes.Structure):
@@ -107,6 +109,17 @@ class LinkProfile(ctypes.Structure):
         ("request_unit", ctypes.c_uint32),
         ("latency_us", ctypes.c_double),
         ("buffer_bytes", ctypes.c_uint64),
+        ("waves", ctypes.c_uint32 * CALIB_WAVES),
+        ("waves_GBps", ctypes.c_double * CALIB_WAVES),
+        ("knee_waves", ctypes.c_uint32),
+        ("offset_bytes", ctypes.c_uint32 * CALIB_OFFSETS),
+        ("offset_GBps", ctypes.c_double * CALIB_OFFSETS),
+        ("nc_memcpy_GBps", ctypes.c_double),
+        ("nc_seq_read_GBps", ctypes.c_double),
+        ("nc_rand_GBps", ctypes.c_double),
+        ("coh_rand_GBps", ctypes.c_double),
+        ("hbm_read_GBps", ctypes.c_double),
+        ("hbm_copy_GBps", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -118,6 +131,13 @@ class LinkProfile(ctypes.Structure):
             "request_unit": self.request_unit,
             "latency_us": self.latency_us,
             "buffer_bytes": self.buffer_bytes,
+            "waves_GBps": dict(zip(list(self.waves), list(self.waves_GBps))),
+            "knee_waves": self.knee_waves,
+            "offset_GBps": dict(zip(list(self.offset_bytes), list(self.offset_GBps))),
+            "noncoherent": {"memcpy_GBps": self.nc_memcpy_GBps, "seq_read_GBps": self.nc_seq_read_GBps,
+                            "rand_GBps": self.nc_rand_GBps, "coherent_rand_GBps": self.coh_rand_GBps},
+            "hbm_read_GBps": self.hbm_read_GBps,
+            "hbm_copy_GBps": self.hbm_copy_GBps,
         }
 
 
@@ -306,11 +326,13 @@ class Graph:
     weights: uint32[E] or None.  With ``borrow`` the edge arrays must be
     PinnedArray objects and are used in place (host zero-copy only).  With
     ``pack`` the lists (ascending) are stored compressed and col is read only
-    here (``EMOGI_F_PACK``).
+    here (``EMOGI_F_PACK``).  ``weight_bound`` computes the SSSP weight-read
+    bounds at creation (``EMOGI_F_WEIGHT_BOUND``; a pass over the weights).
     """
 
     def __init__(self, row_ptr, col, weights=None, placement="host_zero_copy",
-                 symmetric=False, validate=False, borrow=False, noncoherent=False, pack=False):
+                 symmetric=False, validate=False, borrow=False, noncoherent=False, pack=False,
+                 weight_bound=False):
         rp = np.ascontiguousarray(row_ptr, dtype=np.uint64)
         col_arr = col.array if isinstance(col, PinnedArray) else np.ascontiguousarray(col)
         if col_arr.dtype not in (np.uint32, np.uint64):
@@ -322,7 +344,7 @@ class Graph:
         self._keep = (rp, col, weights)
         flags = ((F_SYMMETRIC if symmetric else 0) | (F_VALIDATE if validate else 0)
                  | (F_BORROW if borrow else 0) | (F_PIN_NONCOHERENT if noncoherent else 0)
-                 | (F_PACK if pack else 0))
+                 | (F_PACK if pack else 0) | (F_WEIGHT_BOUND if weight_bound else 0))
         h = ctypes.c_void_p()
         V = rp.shape[0] - 1
         check(lib().emogi_graph_create(rp.ctypes.data, V, _addr(col), col_arr.dtype.itemsize,

@@ -269,8 +269,10 @@ def test_sssp_incoming_weight_bound(gpu_device):
     out = torch.empty(V, dtype=torch.int32, device="cuda")
     exp = oracle.dijkstra(rp, col, w, 0)
     assert list(exp[:8]) == [0, 2, 1, 202, 502, 513, 257, 520]
-    for placement in ("host_zero_copy", "hbm"):
-        with E.Graph(rp, col, w, placement=placement) as G:
+    for placement, bound in (("host_zero_copy", True), ("hbm", True), ("host_zero_copy", False)):
+        with E.Graph(rp, col, w, placement=placement, weight_bound=bound) as G:
+            # the incoming-weight pass runs only when asked for, and only for zero-copy lists
+            assert (G.setup_ms() > 0) == (bound and placement == "host_zero_copy")
             for delta in (0, 1, 3, 1000):
                 G.set_sssp_delta(delta)
                 for v in range(6):
