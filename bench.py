@@ -139,6 +139,39 @@ def counter_traffic(args, kernel):
     return c["kernels"][kernel]
 
 
+def host_cpu():
+    """CPU model and the logical CPUs this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+
+
+def link_rate_violations(result, peak, slack=1.05):
+    """Every host-link rate in the line (keys ending in link_GBps or
+    scan_GBps) that exceeds the measured copy peak by more than `slack`:
+    such a rate counts bytes the timed kernels did not move."""
+    bad = []
+
+    def walk(x, path):
+        if isinstance(x, dict):
+            for k, v in x.items():
+                p = f"{path}.{k}" if path else k
+                if isinstance(v, (int, float)) and (k.endswith("link_GBps") or k == "scan_GBps"):
+                    if v > slack * peak:
+                        bad.append((p, v))
+                else:
+                    walk(v, p)
+
+    walk(result, "")
+    return bad
+
+
 def cpu_baseline(args):
     """The oracle, as it stands, on a bounded sample of the same workload."""
     import graphgen
@@ -178,6 +211,7 @@ def cpu_baseline(args):
     names = {"bfs": "queue BFS", "sssp": "binary-heap Dijkstra", "cc": "union-find CC"}
     return {
         "value": edges / secs / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+        "threads_used": 1, "host_cpu": host_cpu(),
         "sample": (f"single-threaded oracle ({' + '.join(names[a] for a in args.algos)}) on "
                    f"{kind} from the same generator and seeds, one source, {reps} repetition(s); {secs:.1f}s of CPU ("
                    + ", ".join(f"{a} {t:.1f}s" for a, t in times.items()) + ")"),
@@ -247,16 +281,35 @@ def base_result(args, value, elapsed, V, M, profile):
             "preset": args.config, "vertices": V, "directed_edges": M, "col_bytes": args.col_bytes,
             "placement": "host_zero_copy", "request_unit": args.request_unit, "packed": bool(args.pack),
         },
-        "host_link": {
-            "pinned_memcpy_peak_GBps": round(profile["memcpy_GBps"], 2),
-            "request_unit_measured": profile["request_unit"],
-            "kernel_seq_read_GBps": round(max(profile["seq_read_GBps"].values()), 2),
-            "latency_us": round(profile["latency_us"], 3),
-        },
+        "host_link": host_link_summary(profile),
     }
 
 
-def roofline(args, kernels, peak):
+def host_link_summary(profile):
+    """The calibration (Sec. 3.3's toy study): peaks, R, latency, the
+    waves-in-flight sweep with the knee Little's law predicts, start
+    offsets, and coherent vs non-coherent pinning."""
+    import math
+    R = profile["request_unit"]
+    waves = profile.get("waves_GBps", {})
+    best = max(waves.values()) if waves else 0.0
+    # outstanding R-byte requests needed to carry the sweep's best rate over one round trip
+    model = math.ceil(best * 1e9 * profile["latency_us"] * 1e-6 / R) if best else None
+    nc = profile.get("noncoherent", {})
+    return {
+        "pinned_memcpy_peak_GBps": round(profile["memcpy_GBps"], 2),
+        "request_unit_measured": R,
+        "kernel_seq_read_GBps": round(max(profile["seq_read_GBps"].values()), 2),
+        "latency_us": round(profile["latency_us"], 3),
+        "waves_in_flight_GBps": {str(k): round(v, 2) for k, v in waves.items()},
+        "knee_waves": profile.get("knee_waves"),
+        "littles_law_waves": model,
+        "offset_GBps": {str(k): round(v, 2) for k, v in profile.get("offset_GBps", {}).items()},
+        "noncoherent": {k: round(v, 2) for k, v in nc.items()},
+    }
+
+
+def roofline(args, kernels, peak, profile=None):
     """The dominant kernel: algorithmic link bytes per launch over its
     average HIP-event launch time, against the link's published rate."""
     dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["ms"])
@@ -281,10 +334,39 @@ def roofline(args, kernels, peak):
         r["traffic"] = round(ct["link_bytes_per_dispatch"])
         r["traffic_fetch_write"] = round(ct["fetch_bytes_per_dispatch_scaled"] + ct["write_bytes_per_dispatch"])
         r["traffic_source"] = os.path.relpath(counters_path(args), ROOT)
+        if profile and profile.get("hbm_read_GBps"):
+            # the vertex state's side: GPU-memory bytes per launch (read requests to
+            # DRAM, TCC_EA0_RDREQ_DRAM_32B x 32, + WRITE_SIZE) over the launch time
+            hbm_b = round(ct.get("hbm_read_bytes_per_dispatch", 0) + ct["write_bytes_per_dispatch"])
+            hbm_gbps = hbm_b / (r["avg_launch_ms"] * 1e6)
+            r["hbm"] = {"bytes_per_launch": hbm_b, "achieved_GBps": round(hbm_gbps, 1),
+                        "measured_read_peak_GBps": round(profile["hbm_read_GBps"], 1),
+                        "measured_copy_peak_GBps": round(profile["hbm_copy_GBps"], 1),
+                        "frac_of_read_peak": round(hbm_gbps / profile["hbm_read_GBps"], 4)}
+    return r
+
+
+def bfs_directions(G, src, out):
+    """BFS from src with the per-level direction rule and all top-down."""
+    r = {}
+    for mode in ("auto", "top_down"):
+        G.set_direction(mode)
+        G.bfs(src, out)
+        st = G.stats()
+        r[f"{mode}_ms"] = round(st["total_ms"], 2)
+        if mode == "auto":
+            r["bottom_up_levels"] = st["bottom_up_levels"]
+            r["level_direction"] = st["level_direction"]
+            r["level_ms"] = [round(x, 2) for x in st["level_ms"]]
+        else:
+            r["top_down_level_ms"] = [round(x, 2) for x in st["level_ms"]]
+    G.set_direction("auto")
+    r["speedup"] = round(r["top_down_ms"] / r["auto_ms"], 3)
     return r
 
 
 def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
+    import numpy as np
     V, M = rp.shape[0] - 1, int(rp[-1])
     peak = profile["memcpy_GBps"]
     for i in range(args.warmup):
@@ -303,7 +385,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
 
     # --- throughput ---
     teps_edges = 0
-    per = {a: {"ms": 0.0, "edges": 0, "scan_ms": 0.0, "bytes": 0} for a in args.algos}
+    per = {a: {"ms": 0.0, "edges": 0, "scan_ms": 0.0, "bytes": 0, "sector_bytes": 0} for a in args.algos}
     kernels = {}
     for s, r in steps:
         reached = r["bfs"]["reached_edges"]  # out-degrees of the vertices BFS reached
@@ -315,6 +397,9 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             per[a]["edges"] += e
             per[a]["scan_ms"] += st["expand_ms"]
             per[a]["bytes"] += st["useful_link_bytes"]
+            # the same lists at the link's 32-byte sector granularity (packed: encoded bytes)
+            per[a]["sector_bytes"] += (st["useful_link_bytes"] if args.pack
+                                       else st["id_sector_bytes"] + st["weight_sector_bytes"])
             # algorithmic link bytes per edge of this run (SSSP reads a weight only
             # where the edge can improve its target), spread over its levels
             eb = st["useful_link_bytes"] / max(1, st["edges_scanned"])
@@ -330,36 +415,42 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
     link_gbps = link_bytes / (scan_ms * 1e6) if scan_ms else 0.0
 
     result = base_result(args, value, elapsed, V, M, profile)
-    result["config"].update(sources=sources, scheduler=args.scheduler)
+    result["config"].update(
+        sources=sources, scheduler=args.scheduler,
+        bfs_direction="per level (top-down or bottom-up, alpha 14, beta 24)",
+        create_time_passes=("host encode of the packed lists (untimed, as the paper maps at set-up)" if args.pack
+                            else "none: the lists are mapped as given, no weight bounds (EMOGI_F_WEIGHT_BOUND off)"))
     result["per_algorithm"] = {
         a: {"gteps": round(p["edges"] / (p["ms"] * 1e6), 4) if p["ms"] else None,
             "link_GBps": round(p["bytes"] / (p["scan_ms"] * 1e6), 2) if p["scan_ms"] else None,
+            "sector_link_GBps": round(p["sector_bytes"] / (p["scan_ms"] * 1e6), 2) if p["scan_ms"] else None,
             "ms_per_run": round(p["ms"] / len(steps), 3)}
         for a, p in per.items()
     }
+    if "bfs" in per:
+        result["per_algorithm"]["bfs"]["bottom_up_levels_per_run"] = round(
+            sum(r["bfs"]["bottom_up_levels"] for _, r in steps) / len(steps), 2)
     result["host_link"].update(scan_GBps=round(link_gbps, 2), pct_of_pinned_peak=round(100 * link_gbps / peak, 1))
-    result["roofline"] = roofline(args, kernels, peak)
+    result["roofline"] = roofline(args, kernels, peak, profile)
 
     # --- the two systems patterns, each against the plain method on this GPU ---
     if not args.no_batch and "sssp" in args.algos:
-        plain_bfs_ms = per["bfs"]["ms"] / len(steps)
-        plain_sssp_ms = per["sssp"]["ms"] / len(steps)
+        # 64 sources of log-spaced degrees in one batched call each; the plain
+        # method on these same sources is timed by the batched26 preset
         srcs64 = graphgen.degree_spread_sources(rp, 64, seed=4)
         out64 = torch.empty(len(srcs64) * V, dtype=torch.int32, device="cuda")
-        G.bfs_batch(srcs64, out64)
-        sb = G.stats()
-        G.sssp_batch(srcs64, out64)
-        ss = G.stats()
-        del out64
-        result["batched"] = {
-            "sources": len(srcs64), "source_degrees": "log-spaced 1..max (seed 4)",
-            "bfs_ms": round(sb["total_ms"], 1), "sssp_ms": round(ss["total_ms"], 1),
-            "plain_bfs_ms_x_sources": round(plain_bfs_ms * len(srcs64), 1),
-            "plain_sssp_ms_x_sources": round(plain_sssp_ms * len(srcs64), 1),
-            "bfs_speedup_vs_plain": round(plain_bfs_ms * len(srcs64) / sb["total_ms"], 2),
-            "sssp_speedup_vs_plain": round(plain_sssp_ms * len(srcs64) / ss["total_ms"], 2),
-            "params": G.get_batch_params(),
-        }
+        deg_t = torch.from_numpy(np.diff(rp).astype(np.int64)).to("cuda")
+        bat = {"sources": len(srcs64), "source_degrees": "log-spaced 1..max (seed 4)"}
+        for a in ("bfs", "sssp"):
+            getattr(G, a + "_batch")(srcs64, out64)
+            st = G.stats()
+            o = out64.view(len(srcs64), V)
+            reached = sum(int(((o[i] != -1).to(torch.int64) * deg_t).sum()) for i in range(len(srcs64)))
+            bat[f"{a}_ms"] = round(st["total_ms"], 1)
+            bat[f"{a}_gteps"] = round(reached / (st["total_ms"] * 1e6), 3)
+        bat["params"] = G.get_batch_params()
+        result["batched"] = bat
+        del out64, deg_t
         log(f"[bench] batched: {result['batched']}")
     weights = os.path.join(ROOT, "paper_2006_06890_amd", "scheduler_weights.json")
     if not args.no_learned:
@@ -378,6 +469,11 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             sched[name]["step_ms"] = round(sum(r[a]["total_ms"] for a in r), 2)
         result["schedulers"] = sched
         log(f"[bench] schedulers (one step, source {sources[0]}): {sched}")
+
+    if "bfs" in args.algos and not args.no_arms and not args.pack:
+        G.set_scheduler("heuristic")
+        result["direction"] = {"zero_copy": bfs_directions(G, sources[0], out)}
+        log(f"[bench] direction (zero-copy): {result['direction']['zero_copy']}")
 
     if args.pagerank_iters > 0 and "cc" in args.algos:
         # PageRank (the paper's fourth workload): every iteration streams all lists
@@ -406,6 +502,8 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             r = run_step(G, sources[0], out, args.algos)
             reached = r["bfs"]["reached_edges"]
             ms = sum(r[a]["total_ms"] for a in r)
+            if "direction" in result:
+                result["direction"][f"hbm_tier_{f:g}"] = bfs_directions(G, sources[0], out)
             arms[f"hbm_tier_{f:g}"] = {
                 "tier_vertices": nv, "tier_GB": round(nb / 1e9, 2),
                 "tier_edge_share": round(nb / (M * eb), 4),
@@ -416,6 +514,27 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             log(f"[bench] arm hbm_tier_{f:g}: {arms[f'hbm_tier_{f:g}']}")
         G.set_hbm_tier(0)
     G.close()
+    if not args.no_arms and "sssp" in args.algos and not args.pack:
+        # the optional create-time weight bounds (EMOGI_F_WEIGHT_BOUND): their
+        # pass over col + weights against what they save per SSSP
+        t0 = time.perf_counter()
+        Wb = E.Graph(rp, col, w, placement="host_zero_copy", symmetric=True, borrow=True, weight_bound=True)
+        create_s = time.perf_counter() - t0
+        Wb.set_scheduler("heuristic")
+        Wb.sssp(sources[0], out)
+        with_ms = Wb.stats()["total_ms"]
+        setup_ms = Wb.setup_ms()
+        Wb.close()
+        plain_ms = steps[0][1]["sssp"]["total_ms"]
+        saving = plain_ms - with_ms
+        arms["sssp_weight_bound"] = {
+            "create_s": round(create_s, 2), "in_min_pass_ms": round(setup_ms, 1),
+            "in_min_pass_link_GB": round(M * (args.col_bytes + 4) / 1e9, 2),
+            "sssp_ms_with_bound": round(with_ms, 1), "sssp_ms_without": round(plain_ms, 1),
+            "saving_ms_per_sssp": round(saving, 1),
+            "break_even_sssp_runs": round(setup_ms / saving, 1) if saving > 0 else None,
+        }
+        log(f"[bench] arm sssp_weight_bound: {arms['sssp_weight_bound']}")
     if not args.no_arms:
         for placement in ("hbm", "managed"):
             try:
@@ -431,6 +550,8 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
                 "gteps": round(sum(M if a == "cc" else reached for a in r) / (ms * 1e6), 4),
                 **{f"{a}_ms": round(r[a]["total_ms"], 2) for a in r},
             }
+            if "direction" in result:
+                result["direction"][placement] = bfs_directions(H, sources[0], out)
             H.close()
             log(f"[bench] arm {placement}: {arms[placement]}")
     if not args.no_arms and not args.pack:
@@ -443,6 +564,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             arms["packed"] = {"status": str(e)}
             log(f"[bench] arm packed: {arms['packed']}")
             result["arms"] = arms
+            result["link_rate_violations"] = link_rate_violations(result, peak)
             return result
         create_s = time.perf_counter() - t0
         P.set_scheduler("heuristic")
@@ -468,6 +590,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         log(f"[bench] arm packed: {arms['packed']}")
     if arms:
         result["arms"] = arms
+    result["link_rate_violations"] = link_rate_violations(result, peak)
     return result
 
 

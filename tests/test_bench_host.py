@@ -33,3 +33,29 @@ def test_refusals():
     r = subprocess.run([sys.executable, bench.__file__, "--pack", "--config", "batched26"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0 and "--pack" in r.stderr
+
+
+def test_link_rate_check_flags_rates_above_the_copy_peak():
+    """A link rate above the measured copy peak counts bytes that the timed
+    kernels did not move (the sampled-CC bytes once divided by the time of
+    its later passes only gave 3206 GB/s on a 57 GB/s link)."""
+    line = {"host_link": {"scan_GBps": 41.2, "pinned_memcpy_peak_GBps": 57.3},
+            "per_algorithm": {"bfs": {"link_GBps": 50.1, "sector_link_GBps": 53.0},
+                              "cc": {"link_GBps": 3206.36}},
+            "pagerank": {"link_GBps": 51.3},
+            "arms": {"packed": {"bfs_link_GB": 10.9}}}
+    bad = bench.link_rate_violations(line, 57.28)
+    assert bad == [("per_algorithm.cc.link_GBps", 3206.36)]
+    line["per_algorithm"]["cc"]["link_GBps"] = 59.0  # within 5 % of the peak
+    assert bench.link_rate_violations(line, 57.28) == []
+
+
+def test_host_link_summary_littles_law():
+    """The knee the calibration sweep should show: the sweep's best rate
+    times the round trip, in R-byte requests (Sec. 3.3)."""
+    prof = {"memcpy_GBps": 57.28, "request_unit": 256, "seq_read_GBps": {4: 57.6, 8: 57.6, 16: 56.1},
+            "latency_us": 1.184, "waves_GBps": {16: 3.0, 256: 40.0, 512: 55.0, 1024: 56.0}, "knee_waves": 512,
+            "offset_GBps": {0: 50.0, 16: 30.0, 256: 50.0}, "noncoherent": {"memcpy_GBps": 56.0}}
+    h = bench.host_link_summary(prof)
+    assert h["littles_law_waves"] == 259  # ceil(56e9 * 1.184e-6 / 256)
+    assert h["knee_waves"] == 512 and h["waves_in_flight_GBps"]["1024"] == 56.0
