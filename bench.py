@@ -43,13 +43,13 @@ def log(*a):
 
 
 PRESETS = {
-    "kron27": dict(workload="kron", scale=27, col_bytes=8, sources=8, steps=8, cpu_scale=24,
+    "kron27": dict(workload="kron", scale=27, col_bytes=8, sources=8, steps=8,
                    algos=("bfs", "sssp", "cc")),
-    "kron16": dict(workload="kron", scale=16, col_bytes=4, sources=1, steps=50, cpu_scale=16,
+    "kron16": dict(workload="kron", scale=16, col_bytes=4, sources=1, steps=50,
                    algos=("bfs",)),
-    "uniform27": dict(workload="uniform", scale=27, col_bytes=4, sources=8, steps=8, cpu_scale=22,
+    "uniform27": dict(workload="uniform", scale=27, col_bytes=4, sources=8, steps=8,
                       algos=("bfs", "sssp", "cc")),
-    "batched26": dict(workload="kron", scale=26, col_bytes=4, sources=64, steps=2, cpu_scale=22,
+    "batched26": dict(workload="kron", scale=26, col_bytes=4, sources=64, steps=2,
                       algos=("bfs", "sssp")),
 }
 
@@ -172,49 +172,139 @@ def link_rate_violations(result, peak, slack=1.05):
     return bad
 
 
-def cpu_baseline(args):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
-    import graphgen
+PROFILE_ARGS = "--steps 1 --warmup 0 --no-arms --no-cpu-baseline --no-batch --no-learned --pagerank-iters 0"
+COPY_KERNEL = "k_seq_read<4>"  # the calibration's wave-merged read of 1 GiB of pinned host memory
+
+
+def _short_name(name):
+    """'void emogi::k_balanced<unsigned long, 1>(emogi::ScanArgs, ...)' -> 'k_balanced<unsigned long, 1>'."""
+    n = name.strip()
+    for p in ("void ", "emogi::"):
+        if n.startswith(p):
+            n = n[len(p):]
+    n = n.replace("emogi::", "")
+    depth, out = 0, []
+    for ch in n:  # drop the argument list (the first '(' outside template brackets)
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            break
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    if not rows:
+        sys.exit(f"no *{suffix} under {d}")
+    return rows
+
+
+def summarize_profiles(args):
+    """Writes profiles/<name>.md and the counters JSON bench.py reads, from
+    three rocprofv3 runs of `bench.py <args> PROFILE_ARGS`: --kernel-trace
+    --stats, --pmc FETCH_SIZE, --pmc WRITE_SIZE TCC_EA0_RDREQ_IO_32B_sum
+    TCC_EA0_RDREQ_DRAM_32B_sum.  Counters are scaled by what they read for the
+    copy kernel (1 GiB of pinned host memory read once per dispatch)."""
+    trace_d, fetch_d, io_d = args.summarize
+    stats = _csv_rows(trace_d, "kernel_stats.csv")
+    per = {}
+    for d in (fetch_d, io_d):
+        for r in _csv_rows(d, "counter_collection.csv"):
+            k = _short_name(r["Kernel_Name"])
+            e = per.setdefault(k, {"dispatch_ids": set()})
+            e["dispatch_ids"].add(r["Dispatch_Id"])
+            c = r["Counter_Name"]
+            e[c] = e.get(c, 0.0) + float(r["Counter_Value"])
+            e.setdefault("_n_" + c, set()).add(r["Dispatch_Id"])
+    copy = per.get(COPY_KERNEL)
+    if copy is None:
+        sys.exit(f"the counter runs hold no {COPY_KERNEL} dispatch to scale by")
+    n_copy = len(copy["_n_FETCH_SIZE"])
+    copy_bytes = float(1 << 30)
+    fetch_factor = copy_bytes / (copy["FETCH_SIZE"] * 1024 / n_copy)
+    io_factor = copy_bytes / (copy["TCC_EA0_RDREQ_IO_32B_sum"] * 32 / len(copy["_n_TCC_EA0_RDREQ_IO_32B_sum"]))
+    kernels = {}
+    for k, e in per.items():
+        nf = len(e.get("_n_FETCH_SIZE", ())) or 1
+        ni = len(e.get("_n_TCC_EA0_RDREQ_IO_32B_sum", ())) or 1
+        kernels[k] = {
+            "dispatches": ni,
+            "link_bytes_per_dispatch": e.get("TCC_EA0_RDREQ_IO_32B_sum", 0.0) * 32 * io_factor / ni,
+            "fetch_bytes_per_dispatch_scaled": e.get("FETCH_SIZE", 0.0) * 1024 * fetch_factor / nf,
+            "write_bytes_per_dispatch": e.get("WRITE_SIZE", 0.0) * 1024 / ni,
+            "hbm_read_bytes_per_dispatch": e.get("TCC_EA0_RDREQ_DRAM_32B_sum", 0.0) * 32 / ni,
+        }
+    workload = workload_name(args) + "; one bench step (" + "+".join(a.upper() for a in args.algos) + ")"
+    doc = {"workload": workload, "kernel_sources_sha1": kernel_sources_sha1(),
+           "fetch_factor": fetch_factor, "io_factor": io_factor,
+           "copy_kernel": f"{COPY_KERNEL}, 1 GiB of pinned host memory per dispatch", "kernels": kernels}
+    with open(counters_path(args), "w") as f:
+        json.dump(doc, f, indent=1)
+    flags = f"--config {args.config}" + (" --pack" if args.pack else "")
+    cmd = f"python3 $R/bench.py {flags} {PROFILE_ARGS}"
+    lines = [f"# Kernel trace + counters: {workload}", "",
+             f"Kernel sources sha1 {doc['kernel_sources_sha1']} (the files bench.py hashes).",
+             "Commands (run from /tmp with TMPDIR=/tmp; R = repository root):", "", "```",
+             f"rocprofv3 --kernel-trace --stats -d $R/gpurun_out/trace -o trace --output-format csv -- {cmd}",
+             f"rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/fetch -o fetch --output-format csv -- {cmd}",
+             f"rocprofv3 --pmc WRITE_SIZE TCC_EA0_RDREQ_IO_32B_sum TCC_EA0_RDREQ_DRAM_32B_sum -d $R/gpurun_out/io "
+             f"-o io --output-format csv -- {cmd}",
+             f"python3 $R/bench.py {flags} --summarize $R/gpurun_out/trace $R/gpurun_out/fetch $R/gpurun_out/io "
+             f"--summary-name {args.summary_name}", "```", "",
+             "## rocprofv3 --kernel-trace --stats (top kernels)", "",
+             "| kernel | calls | total ms | avg ms | % |", "|---|---|---|---|---|"]
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in stats[:18]:
+        lines.append(f"| `{r['Name'][:100]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    lines += ["", "## Counters (rocprofv3 --pmc; per dispatch, averaged over each kernel's dispatches)", "",
+              f"Scale factors from `{COPY_KERNEL}` ({n_copy} dispatches x 1 GiB of pinned host memory read once): "
+              f"FETCH_SIZE x {fetch_factor:.3f}, TCC_EA0_RDREQ_IO_32B x 32 B x {io_factor:.3f}.  WRITE_SIZE (the "
+              f"copy kernel writes nothing) and TCC_EA0_RDREQ_DRAM_32B x 32 B (GPU-memory read requests past L2) "
+              f"are taken at face value.", "",
+              "| kernel | dispatches | link GB (IO_32B x 32) | link MB / dispatch | FETCH x factor MB / dispatch "
+              "| WRITE MB / dispatch | GPU-memory read MB / dispatch |", "|---|---|---|---|---|---|---|"]
+    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["link_bytes_per_dispatch"] * kv[1]["dispatches"]):
+        lines.append(f"| `{k}` | {v['dispatches']} | {v['link_bytes_per_dispatch'] * v['dispatches'] / 1e9:.2f} | "
+                     f"{v['link_bytes_per_dispatch'] / 1e6:.2f} | {v['fetch_bytes_per_dispatch_scaled'] / 1e6:.2f} | "
+                     f"{v['write_bytes_per_dispatch'] / 1e6:.2f} | {v['hbm_read_bytes_per_dispatch'] / 1e6:.2f} |")
+    md = os.path.join(ROOT, "profiles", args.summary_name + ".md")
+    with open(md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {md} and {counters_path(args)}")
+
+
+def cpu_baseline(args, rp, col_array, src):
+    """The oracle, as it stands, on a bounded sample of the benchmark's own
+    workload: queue BFS from the step's first source over the very arrays the
+    GPU reads (the pinned buffers, read by the CPU), repeated to >= 5 s on
+    small graphs.  SSSP and CC are not sampled: single-threaded Dijkstra and
+    union-find over billions of edges take minutes."""
     import oracle
-    scale = args.cpu_scale
-    if args.workload == "kron":
-        h = graphgen.rmat(scale, 16, 0.57, 0.19, 0.19, seed=1)
-        kind = f"R-MAT scale {scale}"
-    else:
-        h = graphgen.uniform(scale, (1 << scale) * 32, seed=1)
-        kind = f"uniform random 2^{scale} vertices, 2^{scale} x 32 samples"
-    g = h.to_csr(args.col_bytes, weights=True)
-    h.free()
-    if args.config == "kron16":
-        src = int((g.degrees() > 0).argmax())
-    else:
-        src = graphgen.random_sources(g, 1, seed=2)[0]
-    times = {a: 0.0 for a in args.algos}
-    lv = None
-    reps = 0
-    while reps == 0 or sum(times.values()) < 5.0:  # small samples are repeated to >= 5 s
-        for a in args.algos:
-            t = time.perf_counter()
-            if a == "bfs":
-                lv = oracle.bfs(g.row_ptr, g.col, src)
-            elif a == "sssp":
-                oracle.dijkstra(g.row_ptr, g.col, g.weights, src)
-            else:
-                oracle.cc(g.row_ptr, g.col)
-            times[a] += time.perf_counter() - t
+    secs, reps, lv = 0.0, 0, None
+    while reps == 0 or secs < 5.0:
+        t = time.perf_counter()
+        lv = oracle.bfs(rp, col_array, src)
+        secs += time.perf_counter() - t
         reps += 1
-    if lv is None:
-        lv = oracle.bfs(g.row_ptr, g.col, src)
-    reached = oracle.reached_edges(g.row_ptr, lv)
-    edges = reps * sum(g.num_edges if a == "cc" else reached for a in args.algos)
-    secs = sum(times.values())
-    names = {"bfs": "queue BFS", "sssp": "binary-heap Dijkstra", "cc": "union-find CC"}
+    reached = oracle.reached_edges(rp, lv)
+    M = int(rp[-1])
     return {
-        "value": edges / secs / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+        "value": reps * reached / secs / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
         "threads_used": 1, "host_cpu": host_cpu(),
-        "sample": (f"single-threaded oracle ({' + '.join(names[a] for a in args.algos)}) on "
-                   f"{kind} from the same generator and seeds, one source, {reps} repetition(s); {secs:.1f}s of CPU ("
-                   + ", ".join(f"{a} {t:.1f}s" for a, t in times.items()) + ")"),
+        "sample": (f"single-threaded oracle queue BFS from source {src} on the benchmark's own graph "
+                   f"({workload_name(args)}; {M} directed edges, {reached} reached), read from the same "
+                   f"pinned arrays; {reps} run(s), {secs:.1f}s of CPU.  SSSP and CC not sampled (Dijkstra "
+                   f"and union-find over this graph take minutes on one core)"),
+        "compare_with": "per_algorithm.bfs.gteps" if args.config != "batched26" else "batched.bfs.plain_gteps",
     }
 
 
@@ -243,10 +333,12 @@ def parse_args():
                     help="PageRank iterations run once after the timed region (0: skip)")
     ap.add_argument("--tier-fracs", default="0.1,0.25",
                     help="HBM tier budgets (fractions of the edge-list bytes) run as extra arms; '' for none")
-    ap.add_argument("--cpu-scale", type=int, default=None)
     ap.add_argument("--calib-bytes", type=int, default=1 << 30)
     ap.add_argument("--calibrate-only", action="store_true",
                     help="run the link calibration (plain zero-copy read kernels) and exit")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "IO_DIR"),
+                    help="write the profile summary and counters file from three rocprofv3 runs (no GPU)")
+    ap.add_argument("--summary-name", default=None, help="with --summarize: profiles/<name>.md")
     args = ap.parse_args()
     if args.pack:
         if args.config == "batched26":
@@ -256,7 +348,7 @@ def parse_args():
     preset = PRESETS[args.config]
     args.workload = preset["workload"]
     args.algos = preset["algos"]
-    for k in ("scale", "col_bytes", "sources", "steps", "cpu_scale"):
+    for k in ("scale", "col_bytes", "sources", "steps"):
         if getattr(args, k) is None:
             setattr(args, k, preset[k])
     return args
@@ -671,6 +763,11 @@ def bench_batched(args, E, G, rp, sources, profile, torch):
 
 def main():
     args = parse_args()
+    if args.summarize:
+        if not args.summary_name:
+            sys.exit("--summarize needs --summary-name")
+        summarize_profiles(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(sharding over several GPUs is described in the design notes, not implemented)",
@@ -717,11 +814,15 @@ def main():
         out = torch.empty(V, dtype=torch.int32, device="cuda")
         result = bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen)
 
-    col.free()
-    w.free()
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the CPU sample")
-        result["cpu_baseline"] = cpu_baseline(args)
+        if args.config == "batched26":
+            first = graphgen.random_sources(graphgen.CSR(rp, col.array), 1, seed=2)[0]
+        else:
+            first = sources[0]
+        result["cpu_baseline"] = cpu_baseline(args, rp, col.array, first)
+    col.free()
+    w.free()
     print(json.dumps(result), flush=True)
 
 

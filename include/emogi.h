@@ -238,8 +238,10 @@ emogi_status_t emogi_set_scheduler(emogi_graph_t g, int mode);
  * variant (the fixed one, else a workgroup per vertex below 2^24 edges and
  * the heuristic's pick for the whole graph above) and
  * pushes through the LDS-staged queue; 0 (default): 8 on graphs of fewer
- * than 2^24 edges, 1 above.  Always 1 when the scheduler records features,
- * runs the network or probes.  Results are identical. */
+ * than 2^24 edges, 1 above.  Always 1 when the scheduler records features
+ * (EMOGI_SCHED_RECORD) or probes; under EMOGI_SCHED_LEARNED the batches stay
+ * and the network picks the variant only of levels run one per host wait
+ * (stats.levels_by_network counts them).  Results are identical. */
 emogi_status_t emogi_set_level_batch(emogi_graph_t g, uint32_t levels);
 /* SSSP distance band (near-far worklist): every vertex whose distance
  * improves is marked; a round expands, in ascending id order, the marked

@@ -106,7 +106,7 @@ struct BatchPool {
     unsigned long long *vis = nullptr;    // BFS: sources that reached v
     unsigned long long *ovf = nullptr;    // SSSP: sources whose relaxation into v overflowed
     unsigned long long *wait = nullptr;   // SSSP: sources waiting for a later band at v
-    uint32_t *dist = nullptr;             // SSSP: distances, vertex-major [V][64]
+    uint32_t *dist = nullptr;             // BFS levels / SSSP distances, vertex-major [V][64]
     uint32_t *hub[2] = {nullptr, nullptr};// queues of long lists (workgroup per vertex)
     unsigned long long *ctr = nullptr;    // queue lengths, level, flags
     unsigned long long *host_ctr = nullptr;

@@ -33,12 +33,21 @@ __device__ __forceinline__ uint64_t packed_weight_words(uint64_t d, uint32_t ww)
     return (nb - 1) * 2 * uint64_t(ww) + (last * ww + 31) / 32;
 }
 
-// Inclusive prefix sum over the 64 lanes (every lane calls it).
+// Inclusive prefix sum over the 64 lanes (every lane calls it), on DPP lane
+// moves inside the VALU adds (no LDS traffic): shifts by 1, 2, 4 and 8 lanes
+// within each row of 16 (lanes shifted in from outside the row read 0) give
+// each row's own prefix; then lane 15's sum is broadcast into rows 1 and 3
+// and lane 31's (the sum of rows 0-1) into rows 2 and 3.  Masked-off rows
+// take the `old` value 0.
 __device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t x, int lane) {
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-    }
+    (void)lane;
+    constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 1, 0xf, 0xf, true));
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 2, 0xf, 0xf, true));
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 4, 0xf, 0xf, true));
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 8, 0xf, 0xf, true));
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowBcast15, 0xa, 0xf, false));
+    x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowBcast31, 0xc, 0xf, false));
     return x;
 }
 

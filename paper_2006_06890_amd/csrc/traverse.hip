@@ -1387,10 +1387,12 @@ static void use_packed(ScanArgs &s, const emogi_graph_s *g) {
 // Levels per host wait for BFS: the setting, or (0) 8 on graphs of fewer
 // than 2^24 edges and 1 above (measured on R-MAT 16/18/20: batches win up to
 // scale 18; at scale 20 the ordered per-level frontier is worth more than the
-// saved waits); always 1 when the scheduler needs per-level features or
-// timings.
+// saved waits); always 1 when per-level features are recorded or every
+// variant is timed.  The learned scheduler keeps the batches: the host does
+// not see a batch's frontiers, so the batch rule picks their variant and the
+// network decides the levels that run one per host wait.
 static uint32_t level_batch(const emogi_graph_s *g) {
-    if (sched_needs_features(g) || g->sched_mode == EMOGI_SCHED_PROBE || g->packed.stream) return 1;
+    if (g->record_features || g->sched_mode == EMOGI_SCHED_PROBE || g->packed.stream) return 1;
     if (g->level_batch) return g->level_batch;
     return g->E < (uint64_t(1) << 24) ? 8u : 1u;
 }

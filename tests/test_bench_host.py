@@ -17,6 +17,18 @@ def test_kernel_names_match_the_profiler():
     assert bench.kernel_key("bfs", 2, 4, packed=True) == "k_balanced_packed<0>"  # packed: V5 only
 
 
+def test_profiler_names_shorten_to_kernel_keys():
+    """The counter file is keyed by kernel_key's names: the summarizer drops
+    the return type, the namespace and the argument list."""
+    assert bench._short_name("void emogi::k_balanced<unsigned long, 1>(emogi::ScanArgs, emogi::OpArgs)") == \
+        bench.kernel_key("sssp", 5, 8)
+    assert bench._short_name("void emogi::k_bu_probe<unsigned int>(emogi::BuArgs)") == \
+        bench.kernel_key("bfs", 6, 4)
+    assert bench._short_name("emogi::k_bits_count(unsigned int const*, unsigned long)") == "k_bits_count"
+    assert bench._short_name("void emogi::k_balanced_packed<0>(emogi::ScanArgs, emogi::OpArgs)") == \
+        bench.kernel_key("bfs", 5, 8, packed=True)
+
+
 def test_counter_files_and_workload_names():
     a = argparse.Namespace(config="kron27", col_bytes=8, pack=False, workload="kron", scale=27)
     assert bench.counters_path(a).endswith("profiles/counters_kron27_u64.json")

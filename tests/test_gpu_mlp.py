@@ -94,6 +94,8 @@ def test_learned_picks_match_oracle_network(gpu_device):
     with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True) as G:
         G.set_scheduler_weights(theta)
         G.set_scheduler("learned", record=True)
+        # every level top-down: a bottom-up level has no access variant to pick
+        G.set_direction("top_down")
         for algo in ("bfs", "sssp", "cc"):
             if algo == "cc":
                 G.cc(out)
@@ -146,6 +148,7 @@ def test_learned_scheduler_keeps_to_training_range(gpu_device):
     hub = int(g.degrees().max()) > 4096
     with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True) as G:
         G.set_scheduler("learned", record=True)
+        G.set_direction("top_down")  # every level picks an access variant
         # an empty range: every level falls back to the heuristic
         G.set_scheduler_weights(theta, np.full(16, 2.0), np.full(16, -1.0))
         for algo in ("bfs", "sssp"):

@@ -311,6 +311,7 @@ def test_bfs_level_batches(gpu_device, name, batch):
         rp, col, w = _with_col(g, col_bytes)
         with E.Graph(rp, col, w, placement="host_zero_copy", symmetric=True) as G:
             G.set_level_batch(batch)
+            G.set_direction("top_down")  # one level per wait would otherwise run bottom-up levels
             for v in VARIANTS:
                 G.set_variant(v)
                 for s in _sources(g):
