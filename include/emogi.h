@@ -316,6 +316,26 @@ emogi_status_t emogi_bfs(emogi_graph_t g, uint64_t src, uint32_t *levels, void *
 emogi_status_t emogi_sssp(emogi_graph_t g, uint64_t src, uint32_t *dist, void *stream);
 emogi_status_t emogi_cc(emogi_graph_t g, uint32_t *labels, void *stream);
 
+/* BFS that allocates nothing, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same result as emogi_bfs: levels (device uint32[V], caller
+ * owned) receives the level of every vertex, 0xFFFFFFFF when unreachable.
+ * The same level kernels run top-down, 8 levels enqueued per host wait; the
+ * variant is the fixed scheduler variant if one of V0..V4 is set, else a
+ * workgroup per vertex.  Every device buffer it needs (two frontier queues,
+ * the visited bitmap, level counters) lives in a 34 MiB array in the
+ * library's device code, one per GPU, held until the process ends; the call
+ * makes no hipMalloc, hipFree or other allocating call.
+ * Limits and errors: V <= 2^22 (4,194,304) vertices, else EMOGI_E_INVALID;
+ * packed graphs (EMOGI_F_PACK) EMOGI_E_UNSUPPORTED; src >= V or an output
+ * that is not device memory EMOGI_E_INVALID; the graph's device must be the
+ * current device (else EMOGI_E_INVALID).  All calls on one GPU share its
+ * array, which keeps the last call's contents (each call clears what must
+ * start at zero): calls that overlap on one GPU, from several threads or
+ * streams, race and give undefined results.  Returns after the traversal has
+ * completed; emogi_last_stats reports it (levels, edges, link bytes, times). */
+emogi_status_t emogi_bfs_noalloc(emogi_graph_t g, uint64_t src, uint32_t *levels, void *stream);
+
 /* PageRank (the fourth workload of Sec. 5.1), pull form on an undirected
  * graph (created with EMOGI_F_SYMMETRIC, else EMOGI_E_NOT_SYMMETRIC), in
  * fixed point so that every sum is exact: scores are uint64 with

@@ -2233,6 +2233,157 @@ static emogi_status_t pagerank(emogi_graph_s *g, uint32_t iters, uint32_t F, uin
     return EMOGI_OK;
 }
 
+// Bytes of device scratch bfs_in_scratch needs for V vertices: two frontier
+// queues (V ids each), the visited bitmap and one counter block per level of
+// a batch, each part starting on a 256-byte boundary.
+static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+constexpr uint32_t kScratchLevels = 8;  // levels enqueued per host wait
+
+uint64_t bfs_scratch_bytes(uint64_t V) {
+    const uint64_t v = std::max<uint64_t>(V, 1);
+    return 2 * align256(v * 4) + align256(((v + 31) / 32) * 4) +
+           align256(uint64_t(kScratchLevels) * C_COUNT * sizeof(unsigned long long));
+}
+
+// BFS whose every device buffer lives in `scratch` (bytes >= bfs_scratch_bytes(V)):
+// the same level kernels as emogi_bfs, with kScratchLevels levels enqueued per
+// host wait (each level reads the frontier length the previous one left on
+// the device, as in emogi_bfs's level batches), top-down, pushes through the
+// LDS-staged queue, the variant fixed for the traversal (a fixed scheduler
+// variant V0..V4 if set, else a workgroup per vertex).  Allocates nothing: the
+// counters come back through a host array on this thread's stack.
+// Stats: levels, variants, frontiers, edges, link bytes and times.
+emogi_status_t bfs_in_scratch(emogi_graph_s *g, uint64_t src, uint32_t *out, void *scratch, uint64_t bytes,
+                              hipStream_t stream) {
+    if (!g || !out || !scratch) {
+        set_error("null graph, output or scratch");
+        return EMOGI_E_INVALID;
+    }
+    if (src >= g->V) {
+        set_error("source %llu out of range (V = %llu)", (unsigned long long)src, (unsigned long long)g->V);
+        return EMOGI_E_INVALID;
+    }
+    if (g->packed.stream) {
+        set_error("packed lists are scanned by the edge-balanced variant, whose chunk prefix has no room here");
+        return EMOGI_E_UNSUPPORTED;
+    }
+    {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, out) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();
+            set_error("output must be device memory");
+            return EMOGI_E_INVALID;
+        }
+    }
+    const uint64_t V = g->V;
+    if (bytes < bfs_scratch_bytes(V)) {
+        set_error("BFS over %llu vertices needs %llu scratch bytes, %llu available", (unsigned long long)V,
+                  (unsigned long long)bfs_scratch_bytes(V), (unsigned long long)bytes);
+        return EMOGI_E_INVALID;
+    }
+    char *base = static_cast<char *>(scratch);
+    uint32_t *queue[2];
+    queue[0] = reinterpret_cast<uint32_t *>(base);
+    queue[1] = reinterpret_cast<uint32_t *>(base + align256(V * 4));
+    uint32_t *bitmap = reinterpret_cast<uint32_t *>(base + 2 * align256(V * 4));
+    unsigned long long *ctr =
+        reinterpret_cast<unsigned long long *>(base + 2 * align256(V * 4) + align256(((V + 31) / 32) * 4));
+    unsigned long long host[kScratchLevels * C_COUNT];
+
+    emogi_stats_t &S = g->stats;
+    memset(&S, 0, sizeof(S));
+    S.request_unit = g->request_unit;
+    const int m = g->sched_mode;
+    const int var = (m >= 0 && m < int(EMOGI_V5_BALANCED)) ? m : int(EMOGI_V4_BLOCK);
+    const uint32_t align_elems = std::max<uint32_t>(1, g->request_unit / g->col_bytes);
+
+    EMOGI_HIP_TRY(hipEventRecord(g->ev_begin, stream), EMOGI_E_HIP);
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid(V)), dim3(kBlock), 0, stream, out, V, 0xFFFFFFFFu);
+    zero_async(bitmap, ((V + 31) / 32) * sizeof(uint32_t), stream);
+    hipLaunchKernelGGL(k_seed_source, dim3(1), dim3(64), 0, stream, out, bitmap, queue[0], uint32_t(src), 1);
+    EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+
+    uint64_t n = 1, iter = 0;
+    const uint64_t cap = V + 2;  // a BFS has at most V levels with work
+    int cur = 0;
+    while (n > 0) {
+        if (iter >= cap) {
+            (void)hipStreamSynchronize(stream);
+            set_error("iteration cap %llu reached", (unsigned long long)cap);
+            return EMOGI_E_NOCONVERGE;
+        }
+        const uint32_t k = uint32_t(std::min<uint64_t>(kScratchLevels, cap - iter));
+        zero_async(ctr, size_t(k) * C_COUNT * sizeof(unsigned long long), stream);
+        EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
+        for (uint32_t i = 0; i < k; ++i) {
+            ScanArgs s;
+            s.queue = queue[cur];
+            s.n = i == 0 ? uint32_t(n) : uint32_t(V);  // later levels: V only sizes the grids
+            s.n_dev = i == 0 ? nullptr : &ctr[(i - 1) * C_COUNT + C_NEXT];
+            s.row_ptr = g->row_ptr;
+            s.col = g->col;
+            s.w = g->weights;
+            s.next = queue[cur ^ 1];
+            s.align_mask = uint64_t(align_elems) - 1;
+            s.req_unit = g->request_unit;
+            s.col_bytes = g->col_bytes;
+            s.chunk_scan = nullptr;
+            s.tier = tier_view(g);
+            OpArgs a;
+            a.state = out;
+            a.bitmap = bitmap;
+            a.stamp = nullptr;
+            a.tag = uint32_t(iter + i + 1);
+            a.V = uint32_t(V);
+            a.ctr = &ctr[i * C_COUNT];
+            a.nextbits = nullptr;
+            a.split = 0xFFFFFFFFu;
+            a.farbits = nullptr;
+            a.wmin = 0;
+            if (g->col_bytes == 8)
+                launch_variant<uint64_t, A_BFS>(var, s, a, stream);
+            else
+                launch_variant<uint32_t, A_BFS>(var, s, a, stream);
+            cur ^= 1;
+        }
+        EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
+        EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
+        EMOGI_HIP_TRY(hipMemcpyAsync(host, ctr, size_t(k) * C_COUNT * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, stream),
+                      EMOGI_E_HIP);
+        EMOGI_HIP_TRY(hipStreamSynchronize(stream), EMOGI_E_HIP);
+        float ms = 0.f;
+        EMOGI_HIP_TRY(hipEventElapsedTime(&ms, g->ev_k0, g->ev_k1), EMOGI_E_HIP);
+        S.expand_ms += ms;
+        uint32_t ran = 0;
+        for (uint32_t i = 0; i < k && n > 0; ++i, ++ran) {
+            const unsigned long long *hc = &host[i * C_COUNT];
+            if (iter < EMOGI_MAX_LEVEL_STATS) {
+                S.level_variant[iter] = uint8_t(var);
+                S.level_frontier[iter] = uint32_t(n);
+                S.level_edges[iter] = hc[C_EDGES];
+                S.level_count = uint32_t(iter + 1);
+            }
+            S.variant_hist[var] += 1;
+            S.expand_launches += 1;
+            absorb_counters(S, hc);
+            n = hc[C_NEXT];
+            ++iter;
+        }
+        for (uint32_t i = 0; i < ran; ++i)
+            if (iter - ran + i < EMOGI_MAX_LEVEL_STATS) S.level_ms[iter - ran + i] = ms / float(ran);
+    }
+    S.iterations = uint32_t(iter);
+    S.useful_link_bytes = (S.edges_scanned - S.tier_edges) * g->col_bytes;
+    S.reached_edges = S.edges_scanned;  // top-down BFS scans each reached vertex's list once
+    EMOGI_HIP_TRY(hipEventRecord(g->ev_end, stream), EMOGI_E_HIP);
+    EMOGI_HIP_TRY(hipEventSynchronize(g->ev_end), EMOGI_E_HIP);
+    float total = 0.f;
+    EMOGI_HIP_TRY(hipEventElapsedTime(&total, g->ev_begin, g->ev_end), EMOGI_E_HIP);
+    S.total_ms = total;
+    return EMOGI_OK;
+}
+
 }  // namespace emogi
 
 using namespace emogi;

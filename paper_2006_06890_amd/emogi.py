@@ -237,6 +237,7 @@ def lib():
             "emogi_bfs": (i32, [p, u64, p, p]),
             "emogi_sssp": (i32, [p, u64, p, p]),
             "emogi_cc": (i32, [p, p, p]),
+            "emogi_bfs_noalloc": (i32, [p, u64, p, p]),
             "emogi_pagerank": (i32, [p, u32, u32, u64, p, p]),
             "emogi_last_stats": (i32, [p, ctypes.POINTER(Stats)]),
             "emogi_num_vertices": (u64, [p]),
@@ -452,6 +453,12 @@ class Graph:
     def bfs(self, src, out=None, stream=None):
         out = self._out(out)
         check(lib().emogi_bfs(self._h, int(src), out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def bfs_noalloc(self, src, out, stream=None):
+        """emogi_bfs_noalloc: BFS into `out` (required: nothing is allocated)."""
+        out = self._out(out)
+        check(lib().emogi_bfs_noalloc(self._h, int(src), out.data_ptr(), _stream_handle(stream)))
         return out
 
     def sssp(self, src, out=None, stream=None):
