@@ -83,8 +83,9 @@ def build_graph(args, E, graphgen):
     return rp, col, w
 
 
-def run_step(G, src, out, algos=("bfs", "sssp", "cc")):
-    """The step's traversals (BFS, SSSP from src; CC); per-algorithm stats."""
+def run_step(G, src, out, algos=("bfs", "sssp", "cc"), keep=None):
+    """The step's traversals (BFS, SSSP from src; CC); per-algorithm stats.
+    With `keep` (a dict), each algorithm's output is also copied into it."""
     res = {}
     for a in algos:
         if a == "cc":
@@ -92,7 +93,16 @@ def run_step(G, src, out, algos=("bfs", "sssp", "cc")):
         else:
             getattr(G, a)(src, out)
         res[a] = G.stats()
+        if keep is not None:
+            keep[a] = out.clone()
     return res
+
+
+def outputs_equal(ref, got):
+    """Per algorithm: whether an arm's output equals the plain zero-copy run's
+    (levels, distances and labels are unique, so every arm must match)."""
+    import torch
+    return {a: bool(torch.equal(ref[a], got[a])) for a in got if a in ref}
 
 
 def kernel_key(algo, variant, col_bytes, packed=False):
@@ -207,14 +217,42 @@ def _csv_rows(d, suffix):
     return rows
 
 
-def summarize_profiles(args):
+def _trace_table(stats, top=18):
+    lines = ["| kernel | calls | total ms | avg ms | % |", "|---|---|---|---|---|"]
+    stats = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))
+    for r in stats[:top]:
+        lines.append(f"| `{r['Name'][:100]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    return lines
+
+
+def _summarize_trace_only(args, stats, out_dir):
+    """A kernel-trace summary without counters (--summarize TRACE_DIR - -)."""
+    flags = f"--config {args.config}" + (" --pack" if args.pack else "")
+    extra = " --no-autotune" if args.config == "batched26" else ""
+    cmd = f"python3 $R/bench.py {flags} --steps 1 --warmup 0 --no-cpu-baseline{extra}"
+    lines = [f"# Kernel trace: {workload_name(args)}", "",
+             "Commands (run from /tmp with TMPDIR=/tmp; R = repository root):", "", "```",
+             f"rocprofv3 --kernel-trace --stats -d $R/gpurun_out/trace -o trace --output-format csv -- {cmd}",
+             f"python3 $R/bench.py {flags} --summarize $R/gpurun_out/trace - - --summary-name {args.summary_name}",
+             "```", "", "## rocprofv3 --kernel-trace --stats (top kernels)", ""] + _trace_table(stats)
+    md = os.path.join(out_dir, args.summary_name + ".md")
+    with open(md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {md}")
+
+
+def summarize_profiles(args, out_dir=None):
     """Writes profiles/<name>.md and the counters JSON bench.py reads, from
     three rocprofv3 runs of `bench.py <args> PROFILE_ARGS`: --kernel-trace
     --stats, --pmc FETCH_SIZE, --pmc WRITE_SIZE TCC_EA0_RDREQ_IO_32B_sum
     TCC_EA0_RDREQ_DRAM_32B_sum.  Counters are scaled by what they read for the
     copy kernel (1 GiB of pinned host memory read once per dispatch)."""
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
     trace_d, fetch_d, io_d = args.summarize
     stats = _csv_rows(trace_d, "kernel_stats.csv")
+    if fetch_d == "-" and io_d == "-":
+        return _summarize_trace_only(args, stats, out_dir)
     per = {}
     for d in (fetch_d, io_d):
         for r in _csv_rows(d, "counter_collection.csv"):
@@ -246,7 +284,8 @@ def summarize_profiles(args):
     doc = {"workload": workload, "kernel_sources_sha1": kernel_sources_sha1(),
            "fetch_factor": fetch_factor, "io_factor": io_factor,
            "copy_kernel": f"{COPY_KERNEL}, 1 GiB of pinned host memory per dispatch", "kernels": kernels}
-    with open(counters_path(args), "w") as f:
+    cpath = os.path.join(out_dir, os.path.basename(counters_path(args)))
+    with open(cpath, "w") as f:
         json.dump(doc, f, indent=1)
     flags = f"--config {args.config}" + (" --pack" if args.pack else "")
     cmd = f"python3 $R/bench.py {flags} {PROFILE_ARGS}"
@@ -259,12 +298,7 @@ def summarize_profiles(args):
              f"-o io --output-format csv -- {cmd}",
              f"python3 $R/bench.py {flags} --summarize $R/gpurun_out/trace $R/gpurun_out/fetch $R/gpurun_out/io "
              f"--summary-name {args.summary_name}", "```", "",
-             "## rocprofv3 --kernel-trace --stats (top kernels)", "",
-             "| kernel | calls | total ms | avg ms | % |", "|---|---|---|---|---|"]
-    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    for r in stats[:18]:
-        lines.append(f"| `{r['Name'][:100]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
-                     f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+             "## rocprofv3 --kernel-trace --stats (top kernels)", ""] + _trace_table(stats)
     lines += ["", "## Counters (rocprofv3 --pmc; per dispatch, averaged over each kernel's dispatches)", "",
               f"Scale factors from `{COPY_KERNEL}` ({n_copy} dispatches x 1 GiB of pinned host memory read once): "
               f"FETCH_SIZE x {fetch_factor:.3f}, TCC_EA0_RDREQ_IO_32B x 32 B x {io_factor:.3f}.  WRITE_SIZE (the "
@@ -276,10 +310,10 @@ def summarize_profiles(args):
         lines.append(f"| `{k}` | {v['dispatches']} | {v['link_bytes_per_dispatch'] * v['dispatches'] / 1e9:.2f} | "
                      f"{v['link_bytes_per_dispatch'] / 1e6:.2f} | {v['fetch_bytes_per_dispatch_scaled'] / 1e6:.2f} | "
                      f"{v['write_bytes_per_dispatch'] / 1e6:.2f} | {v['hbm_read_bytes_per_dispatch'] / 1e6:.2f} |")
-    md = os.path.join(ROOT, "profiles", args.summary_name + ".md")
+    md = os.path.join(out_dir, args.summary_name + ".md")
     with open(md, "w") as f:
         f.write("\n".join(lines) + "\n")
-    print(f"wrote {md} and {counters_path(args)}")
+    print(f"wrote {md} and {cpath}")
 
 
 def cpu_baseline(args, rp, col_array, src):
@@ -402,8 +436,10 @@ def host_link_summary(profile):
 
 
 def roofline(args, kernels, peak, profile=None):
-    """The dominant kernel: algorithmic link bytes per launch over its
-    average HIP-event launch time, against the link's published rate."""
+    """The dominant kernel: algorithmic link bytes per launch ((e + 4) per
+    scanned edge for SSSP, e for BFS and CC: the per-unit figures of the
+    measurement plan) over its average HIP-event launch time, against the
+    link's published rate."""
     dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["ms"])
     achieved = dom["bytes"] / (dom["ms"] * 1e6)
     r = {
@@ -418,12 +454,16 @@ def roofline(args, kernels, peak, profile=None):
         "launches": dom["launches"],
         "avg_launch_ms": round(dom["ms"] / max(1, dom["launches"]), 4),
         "algorithmic_bytes_per_launch": round(dom["bytes"] / max(1, dom["launches"])),
+        "sector_model_bytes_per_launch": round(dom.get("sector_bytes", 0) / max(1, dom["launches"])),
     }
     ct = counter_traffic(args, dom_name)
     if ct is not None:
         # host-link bytes per launch from TCC_EA0_RDREQ_IO_32B x 32 B (copy-kernel factor applied);
         # FETCH_SIZE (scaled) + WRITE_SIZE per launch beside it for the HBM side
         r["traffic"] = round(ct["link_bytes_per_dispatch"])
+        if r["sector_model_bytes_per_launch"]:
+            r["counted_over_sector_model"] = round(r["traffic"] / r["sector_model_bytes_per_launch"], 4)
+        r["counted_over_algorithmic"] = round(r["traffic"] / max(1, r["algorithmic_bytes_per_launch"]), 4)
         r["traffic_fetch_write"] = round(ct["fetch_bytes_per_dispatch_scaled"] + ct["write_bytes_per_dispatch"])
         r["traffic_source"] = os.path.relpath(counters_path(args), ROOT)
         if profile and profile.get("hbm_read_GBps"):
@@ -438,12 +478,16 @@ def roofline(args, kernels, peak, profile=None):
     return r
 
 
-def bfs_directions(G, src, out):
-    """BFS from src with the per-level direction rule and all top-down."""
+def bfs_directions(G, src, out, ref_levels=None):
+    """BFS from src with the per-level direction rule and all top-down (with
+    ref_levels: both outputs must equal them, recorded in "levels_equal")."""
+    import torch
     r = {}
     for mode in ("auto", "top_down"):
         G.set_direction(mode)
         G.bfs(src, out)
+        if ref_levels is not None:
+            r.setdefault("levels_equal", {})[mode] = bool(torch.equal(out, ref_levels))
         st = G.stats()
         r[f"{mode}_ms"] = round(st["total_ms"], 2)
         if mode == "auto":
@@ -492,14 +536,22 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             # the same lists at the link's 32-byte sector granularity (packed: encoded bytes)
             per[a]["sector_bytes"] += (st["useful_link_bytes"] if args.pack
                                        else st["id_sector_bytes"] + st["weight_sector_bytes"])
-            # algorithmic link bytes per edge of this run (SSSP reads a weight only
-            # where the edge can improve its target), spread over its levels
-            eb = st["useful_link_bytes"] / max(1, st["edges_scanned"])
+            # algorithmic link bytes per scanned list element: the id, and for
+            # SSSP its weight ((e + 4) per edge, whether or not the scan needed
+            # the weight); packed lists: their encoded bytes.  The sector model
+            # (each list, and each weight read, rounded out to 32-byte sectors)
+            # is spread over the levels by their edges, beside it.
+            if args.pack:
+                eb = st["useful_link_bytes"] / max(1, st["edges_scanned"])
+            else:
+                eb = args.col_bytes + (4 if a == "sssp" else 0)
+            sb = (st["id_sector_bytes"] + st["weight_sector_bytes"]) / max(1, st["edges_scanned"])
             for v, ms, ed in zip(st["level_variant"], st["level_ms"], st["level_edges"]):
                 k = kernel_key(a, v, args.col_bytes, args.pack)
-                kk = kernels.setdefault(k, {"ms": 0.0, "bytes": 0, "launches": 0})
+                kk = kernels.setdefault(k, {"ms": 0.0, "bytes": 0, "launches": 0, "sector_bytes": 0})
                 kk["ms"] += ms
                 kk["bytes"] += ed * eb
+                kk["sector_bytes"] += ed * sb
                 kk["launches"] += 1
     value = teps_edges / elapsed / 1e9
     link_bytes = sum(p["bytes"] for p in per.values())
@@ -525,6 +577,12 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
     result["host_link"].update(scan_GBps=round(link_gbps, 2), pct_of_pinned_peak=round(100 * link_gbps / peak, 1))
     result["roofline"] = roofline(args, kernels, peak, profile)
 
+    # outputs of the plain zero-copy method for the first source, untimed: every
+    # arm below (other placements, tier, packed, batched) must reproduce them
+    ref = {}
+    run_step(G, sources[0], out, args.algos, keep=ref)
+    checks = {}
+
     # --- the two systems patterns, each against the plain method on this GPU ---
     if not args.no_batch and "sssp" in args.algos:
         # 64 sources of log-spaced degrees in one batched call each; the plain
@@ -533,6 +591,9 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         out64 = torch.empty(len(srcs64) * V, dtype=torch.int32, device="cuda")
         deg_t = torch.from_numpy(np.diff(rp).astype(np.int64)).to("cuda")
         bat = {"sources": len(srcs64), "source_degrees": "log-spaced 1..max (seed 4)"}
+        j = int(np.argmax(np.diff(rp)[srcs64]))  # the batch's highest-degree source
+        plain_j = {}
+        run_step(G, srcs64[j], out, ("bfs", "sssp"), keep=plain_j)
         for a in ("bfs", "sssp"):
             getattr(G, a + "_batch")(srcs64, out64)
             st = G.stats()
@@ -540,6 +601,8 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             reached = sum(int(((o[i] != -1).to(torch.int64) * deg_t).sum()) for i in range(len(srcs64)))
             bat[f"{a}_ms"] = round(st["total_ms"], 1)
             bat[f"{a}_gteps"] = round(reached / (st["total_ms"] * 1e6), 3)
+            checks.setdefault("batched", {})[a] = bool(torch.equal(o[j], plain_j[a]))
+        del plain_j
         bat["params"] = G.get_batch_params()
         result["batched"] = bat
         del out64, deg_t
@@ -564,7 +627,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
 
     if "bfs" in args.algos and not args.no_arms and not args.pack:
         G.set_scheduler("heuristic")
-        result["direction"] = {"zero_copy": bfs_directions(G, sources[0], out)}
+        result["direction"] = {"zero_copy": bfs_directions(G, sources[0], out, ref.get("bfs"))}
         log(f"[bench] direction (zero-copy): {result['direction']['zero_copy']}")
 
     if args.pagerank_iters > 0 and "cc" in args.algos:
@@ -591,11 +654,14 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         eb = args.col_bytes + 4
         for f in fracs:
             nv, nb = G.set_hbm_tier(int(f * M * eb))
-            r = run_step(G, sources[0], out, args.algos)
+            got = {}
+            r = run_step(G, sources[0], out, args.algos, keep=got)
+            checks[f"hbm_tier_{f:g}"] = outputs_equal(ref, got)
+            del got
             reached = r["bfs"]["reached_edges"]
             ms = sum(r[a]["total_ms"] for a in r)
             if "direction" in result:
-                result["direction"][f"hbm_tier_{f:g}"] = bfs_directions(G, sources[0], out)
+                result["direction"][f"hbm_tier_{f:g}"] = bfs_directions(G, sources[0], out, ref.get("bfs"))
             arms[f"hbm_tier_{f:g}"] = {
                 "tier_vertices": nv, "tier_GB": round(nb / 1e9, 2),
                 "tier_edge_share": round(nb / (M * eb), 4),
@@ -615,6 +681,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         Wb.set_scheduler("heuristic")
         Wb.sssp(sources[0], out)
         with_ms = Wb.stats()["total_ms"]
+        checks["sssp_weight_bound"] = outputs_equal(ref, {"sssp": out})
         setup_ms = Wb.setup_ms()
         Wb.close()
         plain_ms = steps[0][1]["sssp"]["total_ms"]
@@ -635,7 +702,10 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
                 arms[placement] = {"status": str(e)}
                 continue
             H.set_scheduler("heuristic")
-            r = run_step(H, sources[0], out, args.algos)
+            got = {}
+            r = run_step(H, sources[0], out, args.algos, keep=got)
+            checks[placement] = outputs_equal(ref, got)
+            del got
             reached = r["bfs"]["reached_edges"]
             ms = sum(r[a]["total_ms"] for a in r)
             arms[placement] = {
@@ -643,7 +713,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
                 **{f"{a}_ms": round(r[a]["total_ms"], 2) for a in r},
             }
             if "direction" in result:
-                result["direction"][placement] = bfs_directions(H, sources[0], out)
+                result["direction"][placement] = bfs_directions(H, sources[0], out, ref.get("bfs"))
             H.close()
             log(f"[bench] arm {placement}: {arms[placement]}")
     if not args.no_arms and not args.pack:
@@ -656,6 +726,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             arms["packed"] = {"status": str(e)}
             log(f"[bench] arm packed: {arms['packed']}")
             result["arms"] = arms
+            result["output_checks"] = checks
             result["link_rate_violations"] = link_rate_violations(result, peak)
             return result
         create_s = time.perf_counter() - t0
@@ -663,7 +734,11 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         ids_b, w_b = P.packed_bytes()
         ms_a, edges, tot_ms, link = {}, 0, 0.0, {}
         for s in sources:
-            r = run_step(P, s, out, args.algos)
+            got = {} if s == sources[0] else None
+            r = run_step(P, s, out, args.algos, keep=got)
+            if got is not None:
+                checks["packed"] = outputs_equal(ref, got)
+                del got
             reached = r["bfs"]["reached_edges"]
             for a in r:
                 ms_a[a] = ms_a.get(a, 0.0) + r[a]["total_ms"]
@@ -682,6 +757,14 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         log(f"[bench] arm packed: {arms['packed']}")
     if arms:
         result["arms"] = arms
+    # every arm's outputs against the plain zero-copy run of the same source
+    for k, v in result.get("direction", {}).items():
+        if "levels_equal" in v:
+            checks[f"bfs_direction_{k}"] = v.pop("levels_equal")
+    result["output_checks"] = checks
+    bad = [f"{k}.{a}" for k, v in checks.items() for a, ok in v.items() if not ok]
+    if bad:
+        log(f"[bench] OUTPUT MISMATCH against the plain zero-copy run: {bad}")
     result["link_rate_violations"] = link_rate_violations(result, peak)
     return result
 

@@ -184,45 +184,19 @@ __global__ __launch_bounds__(kBlock) void k_brefill(BatchArgs a) {
     finish_queue(st, q, &a.ctr[B_Q0 + a.cur], lane, wid);
 }
 
-// BFS step for one neighbour v of a vertex whose frontier mask is fm:
-// returns the sources that reach v first at this level (0 if none) and sets
-// *push when v enters the next frontier.
-__device__ __forceinline__ unsigned long long bfs_visit(const BatchArgs &a, unsigned long long fm, uint32_t v,
-                                                        bool *push) {
-    *push = false;
-    if (v >= a.V) return 0ull;
+// BFS step for one neighbour v of a vertex whose frontier mask is fm.
+__device__ __forceinline__ bool bfs_visit(const BatchArgs &a, unsigned long long fm, uint32_t v,
+                                          uint32_t level) {
+    if (v >= a.V) return false;
     const unsigned long long m = fm & ~a.vis[v];
-    if (!m) return 0ull;
+    if (!m) return false;
     const unsigned long long newly = m & ~atomicOr(&a.vis[v], m);
-    if (!newly) return 0ull;
-    *push = atomicOr(&a.next[v], newly) == 0ull;
-    return newly;
-}
-
-// Writes `level` for the sources in each lane's `newly` at its vertex v into
-// the vertex-major table out[v][64]: the wave takes the lanes with visits in
-// turn and stores each one's row with a single 256-byte masked store (lane s
-// writes source s), instead of one scattered 4-byte store per source.
-// All 64 lanes must call it together.
-__device__ __forceinline__ void write_levels(const BatchArgs &a, uint32_t v, unsigned long long newly,
-                                             uint32_t level, int lane) {
-    for (unsigned long long todo = __ballot(newly != 0ull); todo; todo &= todo - 1) {
-        const int k = __builtin_ctzll(todo);
-        const uint32_t vk = __shfl(v, k);
-        const uint32_t lo = __shfl(uint32_t(newly), k), hi = __shfl(uint32_t(newly >> 32), k);
-        const unsigned long long nk = (uint64_t(hi) << 32) | lo;
-        if ((nk >> lane) & 1ull) a.out[uint64_t(vk) * 64 + lane] = level;
+    if (!newly) return false;
+    for (unsigned long long b = newly; b; b &= b - 1) {
+        const int s = __builtin_ctzll(b);
+        a.out[uint64_t(s) * a.V + v] = level;
     }
-}
-
-// One wave-wide batch of neighbours (ok: the lane holds neighbour v): visits,
-// level rows, pushes.
-__device__ __forceinline__ void bfs_visit_wave(const BatchArgs &a, Stage &st, unsigned long long fm, bool ok,
-                                               uint32_t v, uint32_t level, int lane) {
-    bool p = false;
-    const unsigned long long newly = ok ? bfs_visit(a, fm, v, &p) : 0ull;
-    write_levels(a, v, newly, level, lane);
-    push_vertex(a, st, p, v, lane);
+    return atomicOr(&a.next[v], newly) == 0ull;
 }
 
 template <class ColT>
@@ -250,7 +224,8 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_short(BatchArgs a) {
                 const uint64_t rest = e - b - k * kWave;
                 const uint32_t cnt = rest < uint64_t(kWave) ? uint32_t(rest) : uint32_t(kWave);
                 const uint32_t v = packed_block(a.pk, L.w0 + k * L.full, L.w, L.ww, cnt, lane, nullptr);
-                bfs_visit_wave(a, st, fm, uint32_t(lane) < cnt, v, level, lane);
+                const bool p = uint32_t(lane) < cnt && bfs_visit(a, fm, v, level);
+                push_vertex(a, st, p, v, lane);
             }
         } else {
             const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
@@ -268,7 +243,10 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_short(BatchArgs a) {
                     v[k] = ok[k] ? uint32_t(src.col[j - src.shift]) : 0u;
                 }
 #pragma unroll
-                for (int k = 0; k < kBUnroll; ++k) bfs_visit_wave(a, st, fm, ok[k], v[k], level, lane);
+                for (int k = 0; k < kBUnroll; ++k) {
+                    const bool p = ok[k] && bfs_visit(a, fm, v[k], level);
+                    push_vertex(a, st, p, v[k], lane);
+                }
             }
         }
     }
@@ -300,7 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_hub(BatchArgs a) {
                 const uint64_t rest = e - b - k * kWave;
                 const uint32_t cnt = rest < uint64_t(kWave) ? uint32_t(rest) : uint32_t(kWave);
                 const uint32_t v = packed_block(a.pk, L.w0 + k * L.full, L.w, L.ww, cnt, lane, nullptr);
-                bfs_visit_wave(a, st, fm, uint32_t(lane) < cnt, v, level, lane);
+                const bool p = uint32_t(lane) < cnt && bfs_visit(a, fm, v, level);
+                push_vertex(a, st, p, v, lane);
             }
         } else {
             const ListSrc<ColT> src = list_src(a.tier, col, a.w, u, b);
@@ -318,7 +297,10 @@ __global__ __launch_bounds__(kBlock) void k_bbfs_hub(BatchArgs a) {
                     v[k] = ok[k] ? uint32_t(src.col[j - src.shift]) : 0u;
                 }
 #pragma unroll
-                for (int k = 0; k < 2; ++k) bfs_visit_wave(a, st, fm, ok[k], v[k], level, lane);
+                for (int k = 0; k < 2; ++k) {
+                    const bool p = ok[k] && bfs_visit(a, fm, v[k], level);
+                    push_vertex(a, st, p, v[k], lane);
+                }
             }
         }
     }
@@ -530,10 +512,12 @@ __global__ void k_bseed(BatchArgs a, const uint64_t *srcs, int sssp) {
     if (blockIdx.x != 0 || s >= a.n) return;
     const uint32_t v = uint32_t(srcs[s]);
     const unsigned long long bit = 1ull << s;
-    a.out[uint64_t(v) * 64 + s] = 0;
     if (sssp) {
+        a.out[uint64_t(v) * 64 + s] = 0;
         if (s == 0) a.ctr[B_SPLIT] = a.delta ? a.delta : kInf;
-    } else {
+    }
+    else {
+        a.out[uint64_t(s) * a.V + v] = 0;
         atomicOr(&a.vis[v], bit);
     }
     if (atomicOr(&a.front[v], bit) == 0ull) {
@@ -543,7 +527,7 @@ __global__ void k_bseed(BatchArgs a, const uint64_t *srcs, int sssp) {
     }
 }
 
-// Vertex-major levels / distances [V][64] -> out[s][V] through a 64x64 LDS tile.
+// dist[V][64] -> out[s][V] through a 64x64 LDS tile.
 __global__ __launch_bounds__(256) void k_btranspose(const uint32_t *dist, uint32_t *out, uint64_t V,
                                                     uint32_t n) {
     __shared__ uint32_t tile[64][65];
@@ -600,10 +584,10 @@ static emogi_status_t ensure_batch(emogi_graph_s *g, bool sssp) {
     }
     if ((st = dalloc(reinterpret_cast<void **>(&b.ctr), B_COUNT * 8)) != EMOGI_OK) return st;
     if ((st = dalloc(reinterpret_cast<void **>(&b.srcs), 64 * 8)) != EMOGI_OK) return st;
-    if ((st = dalloc(reinterpret_cast<void **>(&b.dist), V * 64 * 4)) != EMOGI_OK) return st;
     if (sssp) {
         if ((st = dalloc(reinterpret_cast<void **>(&b.ovf), V * 8)) != EMOGI_OK) return st;
         if ((st = dalloc(reinterpret_cast<void **>(&b.wait), V * 8)) != EMOGI_OK) return st;
+        if ((st = dalloc(reinterpret_cast<void **>(&b.dist), V * 64 * 4)) != EMOGI_OK) return st;
     } else {
         if ((st = dalloc(reinterpret_cast<void **>(&b.vis), V * 8)) != EMOGI_OK) return st;
     }
@@ -676,7 +660,7 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
     a.vis = b.vis;
     a.ovf = b.ovf;
     a.wait = b.wait;
-    a.out = b.dist;  // vertex-major [V][64]; transposed into `out` at the end
+    a.out = sssp ? b.dist : out;
     a.ctr = b.ctr;
     a.n = n;
     a.V = V;
@@ -693,12 +677,14 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
     hipLaunchKernelGGL(k_bfill64, dim3(grid_for(B_COUNT)), dim3(256), 0, s, b.ctr, uint64_t(B_COUNT));
     for (int i = 0; i < 2; ++i)
         hipLaunchKernelGGL(k_bfill64, dim3(grid_for(V)), dim3(256), 0, s, b.mask[i], V);
-    hipLaunchKernelGGL(k_bfill32, dim3(grid_for(V * 64)), dim3(256), 0, s, b.dist, V * 64, kInf);
     if (sssp) {
         hipLaunchKernelGGL(k_bfill64, dim3(grid_for(V)), dim3(256), 0, s, b.ovf, V);
         hipLaunchKernelGGL(k_bfill64, dim3(grid_for(V)), dim3(256), 0, s, b.wait, V);
+        hipLaunchKernelGGL(k_bfill32, dim3(grid_for(V * 64)), dim3(256), 0, s, b.dist, V * 64, kInf);
     } else {
         hipLaunchKernelGGL(k_bfill64, dim3(grid_for(V)), dim3(256), 0, s, b.vis, V);
+        hipLaunchKernelGGL(k_bfill32, dim3(grid_for(uint64_t(n) * V)), dim3(256), 0, s, out,
+                           uint64_t(n) * V, kInf);
     }
     {
         BatchArgs seed = a;
@@ -797,9 +783,9 @@ static emogi_status_t run_batch(emogi_graph_s *g, bool sssp, const uint64_t *src
             EMOGI_HIP_TRY(hipStreamSynchronize(s), EMOGI_E_HIP);
             overflow = (b.host_ctr[B_OVF] & 2ull) != 0;
         }
+        hipLaunchKernelGGL(k_btranspose, dim3(unsigned((V + 63) / 64)), dim3(256), 0, s, b.dist, out, V, n);
+        EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
     }
-    hipLaunchKernelGGL(k_btranspose, dim3(unsigned((V + 63) / 64)), dim3(256), 0, s, b.dist, out, V, n);
-    EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
     EMOGI_HIP_TRY(hipStreamSynchronize(s), EMOGI_E_HIP);
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     emogi_stats_t &S = g->stats;

@@ -44,6 +44,14 @@ enum Counter : int {
     C_COUNT = 22
 };
 
+// Degree bins of the scheduler's frontier histogram: <=1, [2,4), [4,8),
+// [8,16), [16,64), [64,256), [256,4096), >=4096.  The histogram is 8 counts
+// then the degree sum (9 x u64).
+constexpr int kHistBins = 8;
+__device__ __forceinline__ int degree_bin(uint64_t d) {
+    return d <= 1 ? 0 : d < 4 ? 1 : d < 8 ? 2 : d < 16 ? 3 : d < 64 ? 4 : d < 256 ? 5 : d < 4096 ? 6 : 7;
+}
+
 // HBM tier of neighbour lists (device arrays; see tier.h).
 struct Tier {
     uint32_t *bits = nullptr;   // V bits
@@ -106,7 +114,7 @@ struct BatchPool {
     unsigned long long *vis = nullptr;    // BFS: sources that reached v
     unsigned long long *ovf = nullptr;    // SSSP: sources whose relaxation into v overflowed
     unsigned long long *wait = nullptr;   // SSSP: sources waiting for a later band at v
-    uint32_t *dist = nullptr;             // BFS levels / SSSP distances, vertex-major [V][64]
+    uint32_t *dist = nullptr;             // SSSP: distances, vertex-major [V][64]
     uint32_t *hub[2] = {nullptr, nullptr};// queues of long lists (workgroup per vertex)
     unsigned long long *ctr = nullptr;    // queue lengths, level, flags
     unsigned long long *host_ctr = nullptr;

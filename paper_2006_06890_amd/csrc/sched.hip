@@ -19,11 +19,12 @@ int heuristic_variant(const emogi_graph_s *g, uint64_t n);
 
 constexpr int kNIn = 16, kNH = 64, kNOut = 6;
 constexpr int kNParams = kNH * kNIn + kNH + kNH * kNH + kNH + kNOut * kNH + kNOut;  // 5638
-constexpr int kHistBins = 8;
 
 // acc[0..7]: degree histogram of the frontier, acc[8]: sum of degrees.
 // The frontier length is n, or *n_dev when n_dev is set (a frontier the
 // previous level has just written, whose length the host does not know yet).
+// A block adds to acc only the counts it found (small frontiers leave most
+// blocks idle and touch acc from few blocks).
 __global__ __launch_bounds__(256) void k_frontier_hist(const uint32_t *queue, uint64_t n,
                                                        const unsigned long long *n_dev,
                                                        const uint64_t *row_ptr,
@@ -37,9 +38,7 @@ __global__ __launch_bounds__(256) void k_frontier_hist(const uint32_t *queue, ui
          q += uint64_t(gridDim.x) * blockDim.x) {
         const uint32_t u = queue ? queue[q] : uint32_t(q);
         const uint64_t d = row_ptr[u + 1] - row_ptr[u];
-        // bins: <=1, [2,4), [4,8), [8,16), [16,64), [64,256), [256,4096), >=4096
-        int bin = d <= 1 ? 0 : d < 4 ? 1 : d < 8 ? 2 : d < 16 ? 3 : d < 64 ? 4 : d < 256 ? 5 : d < 4096 ? 6 : 7;
-        local[bin] += 1;
+        local[degree_bin(d)] += 1;
         local[kHistBins] += d;
     }
     for (int i = 0; i < kHistBins + 1; ++i)
@@ -52,17 +51,25 @@ struct FeatureConsts {
     float n, V, E, col8, weights, zero_copy, managed;
 };
 
-// One wave: features from the histogram, then z = W3 relu(W2 relu(W1 x + b1) + b2) + b3,
-// argmax into *choice.  The choice is -1 without weights, or when a feature
-// lies outside the range the network was trained on (range: 16 lower, then
-// 16 upper bounds; null: no check), so the caller falls back to the
-// heuristic.  Also stores the features for harvesting, and clears the
-// histogram for its next use.  n_dev as above.
-__global__ __launch_bounds__(64) void k_mlp_pick(unsigned long long *acc, FeatureConsts c,
-                                                 const unsigned long long *n_dev, const float *params,
-                                                 const float *range, int *choice, float *feat_out) {
-    __shared__ float x[kNIn], h1[kNH], h2[kNH], z[kNOut];
+// One workgroup of 256 threads: the 16 features from the histogram, then
+// z = W3 relu(W2 relu(W1 x + b1) + b2) + b3, argmax into *choice.  The
+// parameters are first copied into LDS with coalesced loads (all in flight
+// at once), so the layers wait on one global round trip, not one per input;
+// the 64x64 layer uses four threads per unit.  The choice is -1 without
+// weights, or when a feature lies outside the range the network was trained
+// on (range: 16 lower, then 16 upper bounds; null: no check), so the caller
+// falls back to the heuristic.  Also stores the features for harvesting, and
+// clears the histogram for its next use.  n_dev as above.
+__global__ __launch_bounds__(256) void k_mlp_pick(unsigned long long *acc, FeatureConsts c,
+                                                  const unsigned long long *n_dev, const float *params,
+                                                  const float *range, int *choice, float *feat_out) {
+    __shared__ float P[kNParams];
+    __shared__ float x[kNIn], h1[kNH], part[4][kNH], h2[kNH], z[kNOut];
     const int t = threadIdx.x;
+    if (params) {
+#pragma unroll 8
+        for (int i = t; i < kNParams; i += 256) P[i] = params[i];
+    }
     if (n_dev) c.n = float(*n_dev);
     if (t == 0) {
         const float sumdeg = float(acc[kHistBins]);
@@ -79,32 +86,42 @@ __global__ __launch_bounds__(64) void k_mlp_pick(unsigned long long *acc, Featur
     __syncthreads();
     if (t < kHistBins + 1) acc[t] = 0;
     if (t < kNIn && feat_out) feat_out[t] = x[t];
-    const bool outside = range && t < kNIn && (x[t] < range[t] || x[t] > range[kNIn + t]);
-    if (__ballot(outside) != 0) params = nullptr;  // (uniform) no pick outside the trained range
-    if (!params && t == 0) *choice = -1;
-    const float *W1 = params, *b1 = W1 + kNH * kNIn, *W2 = b1 + kNH, *b2 = W2 + kNH * kNH,
-                *W3 = b2 + kNH, *b3 = W3 + kNOut * kNH;
-    if (params) {
+    const int outside = range && t < kNIn && (x[t] < range[t] || x[t] > range[kNIn + t]);
+    if (__syncthreads_or(outside) || !params) {  // (uniform) no pick outside the trained range
+        if (t == 0) *choice = -1;
+        return;
+    }
+    const float *W1 = P, *b1 = W1 + kNH * kNIn, *W2 = b1 + kNH, *b2 = W2 + kNH * kNH, *W3 = b2 + kNH,
+                *b3 = W3 + kNOut * kNH;
+    if (t < kNH) {
         float a = b1[t];
+#pragma unroll
         for (int k = 0; k < kNIn; ++k) a += W1[t * kNIn + k] * x[k];
         h1[t] = fmaxf(a, 0.f);
-        __syncthreads();
-        a = b2[t];
-        for (int k = 0; k < kNH; ++k) a += W2[t * kNH + k] * h1[k];
-        h2[t] = fmaxf(a, 0.f);
-        __syncthreads();
-        if (t < kNOut) {
-            a = b3[t];
-            for (int k = 0; k < kNH; ++k) a += W3[t * kNH + k] * h2[k];
-            z[t] = a;
-        }
-        __syncthreads();
-        if (t == 0) {
-            int best = 0;
-            for (int j = 1; j < kNOut; ++j)
-                if (z[j] > z[best]) best = j;
-            *choice = best;
-        }
+    }
+    __syncthreads();
+    {
+        const int o = t % kNH, qr = t / kNH;  // unit o, inputs [16 qr, 16 qr + 16)
+        float a = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) a += W2[o * kNH + qr * 16 + k] * h1[qr * 16 + k];
+        part[qr][o] = a;
+    }
+    __syncthreads();
+    if (t < kNH) h2[t] = fmaxf(b2[t] + ((part[0][t] + part[1][t]) + (part[2][t] + part[3][t])), 0.f);
+    __syncthreads();
+    if (t < kNOut) {
+        float a = b3[t];
+#pragma unroll 16
+        for (int k = 0; k < kNH; ++k) a += W3[t * kNH + k] * h2[k];
+        z[t] = a;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int best = 0;
+        for (int j = 1; j < kNOut; ++j)
+            if (z[j] > z[best]) best = j;
+        *choice = best;
     }
 }
 
@@ -118,13 +135,15 @@ struct SchedScratch {
 static emogi_status_t sched_scratch(emogi_graph_s *g, SchedScratch *s) {
     Pool &p = g->pool;
     if (!p.degree_hist) {
-        // layout: [acc: 9 x u64][choice: int][pad][features: 16 f32]
+        // layout: [acc: 9 x u64][pad][choice: int][pad][features: 16 f32]
         if (hipMalloc(&p.degree_hist, 256) != hipSuccess) {
             (void)hipGetLastError();
             p.degree_hist = nullptr;
             set_error("scheduler scratch allocation failed");
             return EMOGI_E_OOM_DEVICE;
         }
+        // k_mlp_pick leaves the histogram cleared after every pick
+        EMOGI_HIP_TRY(hipMemset(p.degree_hist, 0, 256), EMOGI_E_HIP);
     }
     char *base = reinterpret_cast<char *>(p.degree_hist);
     s->acc = reinterpret_cast<unsigned long long *>(base);
@@ -151,27 +170,25 @@ static int learned_pick(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *
                         hipStream_t stream, float *features_host, int *by_network) {
     SchedScratch s;
     if (sched_scratch(g, &s) != EMOGI_OK) return -1;
-    if (hipMemsetAsync(s.acc, 0, 128, stream) != hipSuccess) return -1;
     const unsigned grid = unsigned(std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 1024)));
     hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, n,
                        static_cast<const unsigned long long *>(nullptr), g->row_ptr, s.acc);
-    hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(64), 0, stream, s.acc, feature_consts(g, algo, n),
+    hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(256), 0, stream, s.acc, feature_consts(g, algo, n),
                        static_cast<const unsigned long long *>(nullptr), g->mlp_params, g->mlp_range, s.choice,
                        s.feat);
-    struct {
-        int choice;
-        float feat[kNIn];
-    } h;
-    if (hipMemcpyAsync(&h.choice, s.choice, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipMemcpyAsync(h.feat, s.feat, sizeof(h.feat), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+    // choice (byte 96) and features (bytes 128..191) in one copy
+    unsigned char h[96];
+    if (hipMemcpyAsync(h, s.choice, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess) {
         (void)hipGetLastError();
         return -1;
     }
-    if (features_host) memcpy(features_host, h.feat, sizeof(h.feat));
-    if (!g->mlp_params || h.choice < 0 || h.choice >= kNOut) return heuristic_variant(g, n);  // also: outside range
+    int choice;
+    memcpy(&choice, h, sizeof(int));
+    if (features_host) memcpy(features_host, h + 32, kNIn * sizeof(float));
+    if (!g->mlp_params || choice < 0 || choice >= kNOut) return heuristic_variant(g, n);  // also: outside range
     *by_network = 1;
-    return h.choice;
+    return choice;
 }
 
 // Whether the scheduler needs the frontier's features at all.
@@ -188,19 +205,29 @@ emogi_status_t sched_begin(emogi_graph_s *g, hipStream_t stream) {
     return EMOGI_OK;
 }
 
+// The histogram buffer (9 x u64, cleared by sched_begin and by every pick),
+// for a listing pass that accumulates the next frontier's degrees itself.
+unsigned long long *sched_histogram(emogi_graph_s *g) {
+    SchedScratch s;
+    return sched_scratch(g, &s) == EMOGI_OK ? s.acc : nullptr;
+}
+
 // Features and pick for the frontier a level has just written (its length is
 // counters[C_NEXT] on the device), enqueued behind that level: the results
 // land in the counter block the level copies back anyway, so the choice costs
-// no extra host round trip.  The histogram is left cleared by k_mlp_pick.
+// no extra host round trip.  have_hist: the listing pass that wrote the
+// frontier has already filled the histogram (no pass over the queue here).
+// The histogram is left cleared by k_mlp_pick.
 emogi_status_t sched_prefetch(emogi_graph_s *g, int algo, const uint32_t *queue, unsigned long long *counters,
-                              hipStream_t stream) {
+                              hipStream_t stream, bool have_hist) {
     SchedScratch s;
     emogi_status_t st = sched_scratch(g, &s);
     if (st != EMOGI_OK) return st;
     const unsigned grid = unsigned(std::max<uint64_t>(1, std::min<uint64_t>((g->V + 255) / 256, 1024)));
-    hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, uint64_t(0),
-                       static_cast<const unsigned long long *>(&counters[C_NEXT]), g->row_ptr, s.acc);
-    hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(64), 0, stream, s.acc, feature_consts(g, algo, 0),
+    if (!have_hist)
+        hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, uint64_t(0),
+                           static_cast<const unsigned long long *>(&counters[C_NEXT]), g->row_ptr, s.acc);
+    hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(256), 0, stream, s.acc, feature_consts(g, algo, 0),
                        static_cast<const unsigned long long *>(&counters[C_NEXT]), g->mlp_params, g->mlp_range,
                        reinterpret_cast<int *>(&counters[C_CHOICE]), reinterpret_cast<float *>(&counters[C_FEAT]));
     EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
@@ -233,6 +260,9 @@ int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue
     const int m = g->sched_mode;
     int learned = -2, net = 0;
     *by_network = 0;
+    // a one-vertex frontier (the source) has nothing to schedule: unless its
+    // features are recorded, it takes the heuristic without a host round trip
+    if (!features && m == EMOGI_SCHED_LEARNED && n <= 1) return heuristic_variant(g, n);
     if (features || (m == EMOGI_SCHED_LEARNED && g->mlp_params)) {
         learned = learned_pick(g, algo, n, queue, stream, features, &net);
         if (learned < 0) return -1;

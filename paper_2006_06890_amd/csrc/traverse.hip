@@ -229,10 +229,13 @@ struct ScanArgs {
     const uint8_t *pk_wwidth = nullptr;  // weight width of each packed list, bits (null: no weights)
 };
 
-// V5 chunks loaded per group: a packed block is a short read, so packed
-// scans keep twice as many in flight per wave.
-template <class ColT>
-constexpr int kGroupChunks = kPacked<ColT> ? 8 : 4;
+// V5 chunks loaded per group.  A packed block is a short read, so packed
+// scans keep twice as many in flight per wave; so does SSSP, whose chunks
+// wait on a second link read (the weights) after the first: eight chunks in
+// flight at 4 waves per SIMD measured 2 % faster at R-MAT 26 than four at 6
+// waves (609 against 621 ms), and as fast as two at 8 waves (with spills).
+template <class ColT, int A = A_BFS>
+constexpr int kGroupChunks = (kPacked<ColT> || A == A_SSSP) ? 8 : 4;
 
 __device__ __forceinline__ uint64_t request_bytes(uint64_t s, uint64_t e, uint32_t cb, uint32_t R) {
     uint64_t first = (s * cb) / R, last = (e * cb + R - 1) / R;
@@ -516,9 +519,9 @@ __device__ __forceinline__ void open_run(ChunkCursor<ColT> &c, const ScanArgs &s
 // Issues the loads of the next U chunks (those left in the run) and
 // moves the cursor past them, to the next run when this one is done.
 template <class ColT, int A>
-__device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGroupChunks<ColT>> &g, const ScanArgs &s,
+__device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGroupChunks<ColT, A>> &g, const ScanArgs &s,
                                            const OpArgs &a, int lane, Tally &t) {
-    constexpr int U = kGroupChunks<ColT>;
+    constexpr int U = kGroupChunks<ColT, A>;
 #pragma unroll
     for (int i = 0; i < U; ++i) {
         const uint64_t kk = c.kb + i;
@@ -623,7 +626,7 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGro
 template <class ColT, int A>
 __device__ __forceinline__ void balanced_body(const ScanArgs &s0, const OpArgs &a,
                                               uint32_t (*seg)[kSegCap]) {
-    constexpr int U = kGroupChunks<ColT>;
+    constexpr int U = kGroupChunks<ColT, A>;
     const ScanArgs s = resolved(s0);
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Stage st{seg[wid], 0};
@@ -658,7 +661,7 @@ __device__ __forceinline__ void balanced_body(const ScanArgs &s0, const OpArgs &
 }
 
 template <class ColT, int A>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_balanced(ScanArgs s0,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_balanced(ScanArgs s0,
                                                                                            OpArgs a) {
     __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
     balanced_body<ColT, A>(s0, a, seg);
@@ -1081,10 +1084,13 @@ __global__ __launch_bounds__(kBlock) void k_bits_count(const uint32_t *bits, uin
     }
 }
 
+// hist (optional): the listed vertices' degree histogram for the scheduler
+// (degree_bin counts, then the degree sum), added to *hist.
 __global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t words, const uint32_t *dist,
                                                         uint32_t split, const uint64_t *block_offsets, uint32_t nb,
                                                         uint32_t *queue, uint32_t *also_clear,
-                                                        unsigned long long *ctr) {
+                                                        unsigned long long *ctr, const uint64_t *row_ptr,
+                                                        unsigned long long *hist) {
     const uint64_t base = uint64_t(blockIdx.x) * kBitsTile + uint64_t(threadIdx.x) * kBitsPerThread;
     uint32_t sel[kBitsPerThread];
     uint32_t rest = 0xFFFFFFFFu;  // not used here: k_bits_count reported it
@@ -1113,6 +1119,25 @@ __global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t 
         }
     }
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) ctr[C_NEXT] = block_offsets[blockIdx.x] + tot;
+    if (hist) {
+        __shared__ unsigned long long s_hist[kHistBins + 1];
+        if (threadIdx.x < kHistBins + 1) s_hist[threadIdx.x] = 0;
+        __syncthreads();
+        unsigned long long local[kHistBins + 1] = {};
+#pragma unroll
+        for (int i = 0; i < kBitsPerThread; ++i) {
+            for (uint32_t w = sel[i]; w; w &= w - 1) {
+                const uint64_t v = (base + i) * 32 + uint64_t(__ffs(w) - 1);
+                const uint64_t d = row_ptr[v + 1] - row_ptr[v];
+                local[degree_bin(d)] += 1;
+                local[kHistBins] += d;
+            }
+        }
+        for (int i = 0; i < kHistBins + 1; ++i)
+            if (local[i]) atomicAdd(&s_hist[i], local[i]);
+        __syncthreads();
+        if (threadIdx.x < kHistBins + 1 && s_hist[threadIdx.x]) atomicAdd(&hist[threadIdx.x], s_hist[threadIdx.x]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1452,7 +1477,8 @@ int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue
                    float *features, int *by_network);
 emogi_status_t sched_begin(emogi_graph_s *g, hipStream_t stream);
 emogi_status_t sched_prefetch(emogi_graph_s *g, int algo, const uint32_t *queue, unsigned long long *counters,
-                              hipStream_t stream);
+                              hipStream_t stream, bool have_hist);
+unsigned long long *sched_histogram(emogi_graph_s *g);
 int choose_prefetched(const emogi_graph_s *g, uint64_t n, const unsigned long long *hc, float *features,
                       int *by_network);
 
@@ -1717,13 +1743,17 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     // Lists the marks in `bits` (with `dist`: those below `cut`) into `queue`
     // in id order, also clearing them in `also_clear`; the count lands in
     // counters[C_NEXT], the smallest distance left marked in C_BANDMIN.
+    // with_hist: also fills the scheduler's degree histogram of the listed
+    // frontier (sched_prefetch then needs no pass of its own).
     auto list_marks = [&](uint32_t *bits, const uint32_t *dist, uint32_t cut, uint32_t *queue,
-                          uint32_t *also_clear) {
+                          uint32_t *also_clear, bool with_hist = false) {
+        unsigned long long *hist = with_hist ? sched_histogram(g) : nullptr;
         hipLaunchKernelGGL(k_bits_count, dim3(nbw), dim3(kBlock), 0, stream, bits, words, dist, cut,
                            p.block_sums, p.counters);
         hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nbw);
         hipLaunchKernelGGL(k_bits_write, dim3(nbw), dim3(kBlock), 0, stream, bits, words, dist, cut,
-                           p.block_sums, nbw, queue, also_clear, p.counters);
+                           p.block_sums, nbw, queue, also_clear, p.counters,
+                           static_cast<const uint64_t *>(g->row_ptr), hist);
     };
     auto sync_counters = [&]() -> emogi_status_t {
         EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
@@ -1734,8 +1764,9 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
         return EMOGI_OK;
     };
     // The scheduler's features and pick for the next frontier are computed
-    // behind each level and come back with its counters (have_pick); the
-    // first frontier, and one opened by an SSSP band step, is scored on its own.
+    // behind each level (and behind an SSSP band step's listing) and come
+    // back with its counters (have_pick); the first frontier is scored on its
+    // own.
     // (BFS with bottom-up levels scores each top-down frontier on its own)
     const bool prefetch = V > 0 && sched_needs_features(g) && !(algo == A_BFS && direction_allowed(g));
     bool have_pick = false;
@@ -1869,9 +1900,16 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             const uint64_t m = 0x100000000ull - bm;
             split = uint32_t(std::min<uint64_t>(std::max<uint64_t>(m + delta, split), 0xFFFFFFFFull));
             zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
-            list_marks(p.farbits, out, split, p.queue[cur], nullptr);
+            list_marks(p.farbits, out, split, p.queue[cur], nullptr, prefetch);
+            if (prefetch) {
+                // the band's first frontier is scored behind its listing and its
+                // pick comes back with the counters
+                emogi_status_t e3 = sched_prefetch(g, algo, p.queue[cur], p.counters, stream, true);
+                if (e3 != EMOGI_OK) return e3;
+            }
             if ((st = sync_counters()) != EMOGI_OK) return st;
             n = p.host_counters[C_NEXT];
+            have_pick = prefetch;
             continue;
         }
         if (iter >= cap) {
@@ -1942,11 +1980,12 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
             if (ordered && !do_bfs) {
-                list_marks(p.nextbits, nullptr, 0xFFFFFFFFu, s.next, algo == A_SSSP ? p.farbits : nullptr);
+                list_marks(p.nextbits, nullptr, 0xFFFFFFFFu, s.next, algo == A_SSSP ? p.farbits : nullptr,
+                           prefetch);
                 EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             }
             if (prefetch) {
-                emogi_status_t e3 = sched_prefetch(g, algo, s.next, p.counters, stream);
+                emogi_status_t e3 = sched_prefetch(g, algo, s.next, p.counters, stream, ordered && !do_bfs);
                 if (e3 != EMOGI_OK) return e3;
             }
             EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),

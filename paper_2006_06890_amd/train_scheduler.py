@@ -14,9 +14,10 @@
    library uses the heuristic (the network is not extrapolated).
 3. Evaluate: on held-out locality-ordered power-law graphs (10^8 vertices,
    mean degree 36, exponent 2.1, runs of 1024; seeds 101-103),
-   time each traversal with the fixed aligned-wave variant (the paper's
-   choice), the built-in heuristic, the learned scheduler, and report the
-   per-level best (sum over levels of the fastest variant's probe time).
+   time each traversal (every BFS level top-down, so that the modes differ
+   only in the access variant) with the fixed aligned-wave variant (the
+   paper's choice), the built-in heuristic, the learned scheduler, and report
+   the per-level best (sum over levels of the fastest variant's probe time).
 
 Writes ``scheduler_weights.json`` next to this file:
 ``{"params": [5638 floats], "feature_lo": [16], "feature_hi": [16], "train": {...},
@@ -41,6 +42,7 @@ def log(*a):
 
 
 PINNED_SCALE = 25  # graphs from this scale on are written straight into pinned memory
+EXCLUDED_LABELS = (0,)  # variants never used as labels (see main)
 
 
 class _PinnedGraph:
@@ -111,6 +113,7 @@ def harvest(E, graphgen, specs, torch):
                     for f, p in zip(st["level_features"], st["level_probe_ms"]):
                         X.append(f)
                         T.append(p)
+                    log(f"  {spec} {algo}: {len(st['level_probe_ms'])} levels ({time.time() - t0:.1f}s)")
         log(f"harvested {spec}: {len(X)} levels so far ({time.time() - t0:.1f}s)")
         del g, out  # before the next graph is generated (the largest are 50-70 GB)
     return np.array(X, dtype=np.float32), np.array(T, dtype=np.float32)
@@ -137,6 +140,7 @@ def evaluate(E, graphgen, specs, params, torch, lo=None, hi=None):
         srcs = _sources(g, 2, spec[3] + 5)
         with _open(E, g) as G:
             G.set_scheduler_weights(params, lo, hi)
+            G.set_direction("top_down")  # the modes differ only in the access variant
             for algo in ("bfs", "sssp", "cc"):
                 res = {}
                 for mode in ("fixed_v3", "heuristic", "learned", "probe"):
@@ -176,6 +180,12 @@ def main():
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--eval-vertices", type=int, default=100_000_000)
     ap.add_argument("--out", default=WEIGHTS, help="where to write the weights JSON")
+    ap.add_argument("--harvest-out", metavar="NPZ", help="also save the harvested levels (features, times)")
+    ap.add_argument("--harvest-set", choices=("all", "small", "large"), default="all",
+                    help="harvest every training graph, those below scale 25, or those from 25 on")
+    ap.add_argument("--harvest-only", action="store_true", help="stop after saving the harvest (--harvest-out)")
+    ap.add_argument("--harvest-in", metavar="NPZ", nargs="+",
+                    help="skip harvesting: train on levels saved by --harvest-out (several files are joined)")
     ap.add_argument("--eval-only", metavar="WEIGHTS_JSON",
                     help="skip harvesting and training: evaluate these weights and write them, "
                          "with the new evaluation rows, to --out")
@@ -208,13 +218,35 @@ def main():
         log(f"wrote {args.out}")
         return
 
-    X, T = harvest(E, graphgen, train_specs, torch)
-    y = np.argmin(T, axis=1).astype(np.int32)
+    if args.harvest_in:
+        parts = [np.load(f) for f in args.harvest_in]
+        X = np.concatenate([d["X"] for d in parts])
+        T = np.concatenate([d["T"] for d in parts])
+        train_specs = [json.loads(str(x)) for d in parts for x in d["specs"]]
+    else:
+        if args.harvest_set != "all":
+            large = args.harvest_set == "large"
+            train_specs = [sp for sp in train_specs if (sp[1] >= PINNED_SCALE) == large]
+        X, T = harvest(E, graphgen, train_specs, torch)
+        if args.harvest_out:
+            np.savez(args.harvest_out, X=X, T=T, specs=np.array([json.dumps(list(x)) for x in train_specs]))
+            log(f"saved {X.shape[0]} levels to {args.harvest_out}")
+        if args.harvest_only:
+            return
+    # A thread per vertex (V0) is never a label.  Where it is the fastest it
+    # saves little (87.5 ms over the 8042 levels harvested at R-MAT / uniform
+    # scales 16-27), where it is not it can cost seconds per level (a hub's
+    # list read by one thread: 226 s of regret over the same levels), so a
+    # network that picks it on an unseen graph risks ruinous levels.  The label
+    # is the fastest of the other five variants.
+    allowed = np.array([v for v in range(6) if v not in EXCLUDED_LABELS])
+    y = allowed[np.argmin(T[:, allowed], axis=1)].astype(np.int32)
     log(f"{X.shape[0]} levels; label histogram {np.bincount(y, minlength=6).tolist()}")
     # Cost-sensitive sampling: a level is repeated in proportion to what a wrong
-    # pick can cost there (slowest - fastest variant, in units of 0.05 ms, at
-    # most 40 copies), so cheap levels with noisy labels weigh little.
-    spread = T.max(axis=1) - T.min(axis=1)
+    # pick among the allowed variants can cost there (slowest - fastest, in
+    # units of 0.05 ms, at most 40 copies), so cheap levels with noisy labels
+    # weigh little.
+    spread = T[:, allowed].max(axis=1) - T[:, allowed].min(axis=1)
     copies = 1 + np.minimum(40, np.floor(spread / 0.05)).astype(np.int64)
     Xw, yw = np.repeat(X, copies, axis=0), np.repeat(y, copies)
     # replicate small datasets so every epoch has several full minibatches
@@ -233,6 +265,7 @@ def main():
         "feature_hi": [float(x) for x in hi],
         "train": {"specs": train_specs, "levels": int(X.shape[0]),
                   "label_hist": np.bincount(y, minlength=6).tolist(),
+                  "excluded_labels": list(EXCLUDED_LABELS),
                   "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                   "epochs": args.epochs},
         "eval": rows,

@@ -71,3 +71,48 @@ def test_host_link_summary_littles_law():
     h = bench.host_link_summary(prof)
     assert h["littles_law_waves"] == 259  # ceil(56e9 * 1.184e-6 / 256)
     assert h["knee_waves"] == 512 and h["waves_in_flight_GBps"]["1024"] == 56.0
+
+
+def test_profile_summary_scales_counters_by_the_copy_kernel(tmp_path):
+    """--summarize on synthetic rocprofv3 CSVs: per-dispatch averages, the copy
+    kernel's scale factors (1 GiB read once), kernel names as bench keys them."""
+    import csv
+    for sub in ("t", "f", "i"):
+        (tmp_path / sub / "host").mkdir(parents=True)
+
+    def write(path, header, rows):
+        with open(path, "w", newline="") as f:
+            w = csv.writer(f)
+            w.writerow(header)
+            w.writerows(rows)
+
+    sssp = "void emogi::k_balanced<unsigned long, 1>(emogi::ScanArgs, emogi::OpArgs)"
+    copy = "void emogi::k_seq_read<4>(unsigned char const*, unsigned long, unsigned long long*)"
+    write(tmp_path / "t/host/trace_kernel_stats.csv",
+          ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"],
+          [[sssp, 2, 8e6, 4e6, 80, 1, 1, 0], [copy, 1, 2e6, 2e6, 20, 1, 1, 0]])
+    cc = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    write(tmp_path / "f/host/fetch_counter_collection.csv", cc,
+          [[1, copy, "FETCH_SIZE", 524288], [2, sssp, "FETCH_SIZE", 1000], [3, sssp, "FETCH_SIZE", 3000]])
+    write(tmp_path / "i/host/io_counter_collection.csv", cc,
+          [[1, copy, "TCC_EA0_RDREQ_IO_32B_sum", (1 << 30) // 32], [1, copy, "WRITE_SIZE", 0],
+           [1, copy, "TCC_EA0_RDREQ_DRAM_32B_sum", 0],
+           [2, sssp, "TCC_EA0_RDREQ_IO_32B_sum", 100], [3, sssp, "TCC_EA0_RDREQ_IO_32B_sum", 300],
+           [2, sssp, "WRITE_SIZE", 10], [3, sssp, "WRITE_SIZE", 30],
+           [2, sssp, "TCC_EA0_RDREQ_DRAM_32B_sum", 5], [3, sssp, "TCC_EA0_RDREQ_DRAM_32B_sum", 7]])
+    a = argparse.Namespace(summarize=[str(tmp_path / d) for d in ("t", "f", "i")], summary_name="s",
+                           config="kron27", pack=False, col_bytes=8, workload="kron", scale=27,
+                           algos=("bfs", "sssp", "cc"))
+    bench.summarize_profiles(a, out_dir=str(tmp_path))
+    import json
+    doc = json.load(open(tmp_path / "counters_kron27_u64.json"))
+    assert doc["fetch_factor"] == 2.0 and doc["io_factor"] == 1.0
+    assert doc["kernel_sources_sha1"] == bench.kernel_sources_sha1()
+    k = doc["kernels"][bench.kernel_key("sssp", 5, 8)]
+    assert k["dispatches"] == 2
+    assert k["link_bytes_per_dispatch"] == 200 * 32
+    assert k["fetch_bytes_per_dispatch_scaled"] == 2000 * 1024 * 2.0
+    assert k["write_bytes_per_dispatch"] == 20 * 1024
+    assert k["hbm_read_bytes_per_dispatch"] == 6 * 32
+    md = (tmp_path / "s.md").read_text()
+    assert "rocprofv3 --pmc FETCH_SIZE" in md and "k_balanced<unsigned long, 1>" in md

@@ -186,3 +186,30 @@ def test_probe_mode_exact_and_times_every_variant(gpu_device):
         np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(g.row_ptr, g.col, g.weights, s))
         G.cc(out)
         np.testing.assert_array_equal(E.to_u32(out), oracle.cc(g.row_ptr, g.col))
+
+
+def test_learned_mode_keeps_bfs_level_batches(gpu_device):
+    """On a graph small enough for BFS level batches the learned scheduler
+    keeps them (the batch rule picks the variant, a workgroup per vertex, and
+    the network decides no BFS level), while SSSP levels, run one per host
+    wait, are the network's; results equal the oracle either way."""
+    import torch
+    import paper_2006_06890_amd as E
+    g = graphgen.rmat(12, seed=5).to_csr(4, weights=True)
+    rng = np.random.Generator(np.random.PCG64(3))
+    theta = (rng.standard_normal(mlp.N_PARAMS) * 0.5).astype(np.float32)
+    out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+    s = int(np.argmax(g.degrees()))
+    with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True) as G:
+        G.set_scheduler_weights(theta, np.full(16, -1e30), np.full(16, 1e30))
+        G.set_scheduler("learned")
+        G.bfs(s, out)
+        np.testing.assert_array_equal(E.to_u32(out), oracle.bfs(g.row_ptr, g.col, s))
+        st = G.stats()
+        assert st["levels_by_network"] == 0
+        assert set(st["level_variant"]) == {4}  # level batches: a workgroup per vertex
+        G.sssp(s, out)
+        np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(g.row_ptr, g.col, g.weights, s))
+        st = G.stats()
+        # every SSSP level but the source's one-vertex frontier is the network's pick
+        assert st["levels_by_network"] == len(st["level_variant"]) - 1
