@@ -231,10 +231,11 @@ def _summarize_trace_only(args, stats, out_dir):
     flags = f"--config {args.config}" + (" --pack" if args.pack else "")
     extra = " --no-autotune" if args.config == "batched26" else ""
     cmd = f"python3 $R/bench.py {flags} --steps 1 --warmup 0 --no-cpu-baseline{extra}"
+    td = os.path.basename(os.path.normpath(args.summarize[0]))
     lines = [f"# Kernel trace: {workload_name(args)}", "",
              "Commands (run from /tmp with TMPDIR=/tmp; R = repository root):", "", "```",
-             f"rocprofv3 --kernel-trace --stats -d $R/gpurun_out/trace -o trace --output-format csv -- {cmd}",
-             f"python3 $R/bench.py {flags} --summarize $R/gpurun_out/trace - - --summary-name {args.summary_name}",
+             f"rocprofv3 --kernel-trace --stats -d $R/gpurun_out/{td} -o trace --output-format csv -- {cmd}",
+             f"python3 $R/bench.py {flags} --summarize $R/gpurun_out/{td} - - --summary-name {args.summary_name}",
              "```", "", "## rocprofv3 --kernel-trace --stats (top kernels)", ""] + _trace_table(stats)
     md = os.path.join(out_dir, args.summary_name + ".md")
     with open(md, "w") as f:
@@ -289,14 +290,15 @@ def summarize_profiles(args, out_dir=None):
         json.dump(doc, f, indent=1)
     flags = f"--config {args.config}" + (" --pack" if args.pack else "")
     cmd = f"python3 $R/bench.py {flags} {PROFILE_ARGS}"
+    td, fd, iod = (os.path.basename(os.path.normpath(x)) for x in (trace_d, fetch_d, io_d))
     lines = [f"# Kernel trace + counters: {workload}", "",
              f"Kernel sources sha1 {doc['kernel_sources_sha1']} (the files bench.py hashes).",
              "Commands (run from /tmp with TMPDIR=/tmp; R = repository root):", "", "```",
-             f"rocprofv3 --kernel-trace --stats -d $R/gpurun_out/trace -o trace --output-format csv -- {cmd}",
-             f"rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/fetch -o fetch --output-format csv -- {cmd}",
-             f"rocprofv3 --pmc WRITE_SIZE TCC_EA0_RDREQ_IO_32B_sum TCC_EA0_RDREQ_DRAM_32B_sum -d $R/gpurun_out/io "
+             f"rocprofv3 --kernel-trace --stats -d $R/gpurun_out/{td} -o trace --output-format csv -- {cmd}",
+             f"rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/{fd} -o fetch --output-format csv -- {cmd}",
+             f"rocprofv3 --pmc WRITE_SIZE TCC_EA0_RDREQ_IO_32B_sum TCC_EA0_RDREQ_DRAM_32B_sum -d $R/gpurun_out/{iod} "
              f"-o io --output-format csv -- {cmd}",
-             f"python3 $R/bench.py {flags} --summarize $R/gpurun_out/trace $R/gpurun_out/fetch $R/gpurun_out/io "
+             f"python3 $R/bench.py {flags} --summarize $R/gpurun_out/{td} $R/gpurun_out/{fd} $R/gpurun_out/{iod} "
              f"--summary-name {args.summary_name}", "```", "",
              "## rocprofv3 --kernel-trace --stats (top kernels)", ""] + _trace_table(stats)
     lines += ["", "## Counters (rocprofv3 --pmc; per dispatch, averaged over each kernel's dispatches)", "",

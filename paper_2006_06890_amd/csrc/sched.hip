@@ -52,7 +52,8 @@ struct FeatureConsts {
 };
 
 // One workgroup of 256 threads: the 16 features from the histogram, then
-// z = W3 relu(W2 relu(W1 x + b1) + b2) + b3, argmax into *choice.  The
+// z = W3 relu(W2 relu(W1 x + b1) + b2) + b3, argmax over the eligible
+// variants (the straggler guard below) into *choice.  The
 // parameters are first copied into LDS with coalesced loads (all in flight
 // at once), so the layers wait on one global round trip, not one per input;
 // the 64x64 layer uses four threads per unit.  The choice is -1 without
@@ -118,9 +119,19 @@ __global__ __launch_bounds__(256) void k_mlp_pick(unsigned long long *acc, Featu
     }
     __syncthreads();
     if (t == 0) {
-        int best = 0;
-        for (int j = 1; j < kNOut; ++j)
-            if (z[j] > z[best]) best = j;
+        // Straggler guard: a worker narrower than the frontier's longest list
+        // reads that list alone while the rest of the level waits, so a variant
+        // is eligible only if every list fits it: a thread (V0) below 16 ids,
+        // a 16-lane group (V1) below 64, a wave (V2, V3) below 4096; the
+        // workgroup (V4) and the edge-balanced scan (V5) always are.
+        // (x[4 + b] > 0: some frontier vertex has a degree in bin b.)
+        bool long_at[kHistBins + 1];  // some list in bin b or above
+        long_at[kHistBins] = false;
+        for (int b = kHistBins - 1; b >= 0; --b) long_at[b] = long_at[b + 1] || x[4 + b] > 0.f;
+        const bool eligible[kNOut] = {!long_at[4], !long_at[5], !long_at[7], !long_at[7], true, true};
+        int best = -1;
+        for (int j = 0; j < kNOut; ++j)
+            if (eligible[j] && (best < 0 || z[j] > z[best])) best = j;
         *choice = best;
     }
 }
@@ -205,28 +216,18 @@ emogi_status_t sched_begin(emogi_graph_s *g, hipStream_t stream) {
     return EMOGI_OK;
 }
 
-// The histogram buffer (9 x u64, cleared by sched_begin and by every pick),
-// for a listing pass that accumulates the next frontier's degrees itself.
-unsigned long long *sched_histogram(emogi_graph_s *g) {
-    SchedScratch s;
-    return sched_scratch(g, &s) == EMOGI_OK ? s.acc : nullptr;
-}
-
 // Features and pick for the frontier a level has just written (its length is
 // counters[C_NEXT] on the device), enqueued behind that level: the results
 // land in the counter block the level copies back anyway, so the choice costs
-// no extra host round trip.  have_hist: the listing pass that wrote the
-// frontier has already filled the histogram (no pass over the queue here).
-// The histogram is left cleared by k_mlp_pick.
+// no extra host round trip.  The histogram is left cleared by k_mlp_pick.
 emogi_status_t sched_prefetch(emogi_graph_s *g, int algo, const uint32_t *queue, unsigned long long *counters,
-                              hipStream_t stream, bool have_hist) {
+                              hipStream_t stream) {
     SchedScratch s;
     emogi_status_t st = sched_scratch(g, &s);
     if (st != EMOGI_OK) return st;
     const unsigned grid = unsigned(std::max<uint64_t>(1, std::min<uint64_t>((g->V + 255) / 256, 1024)));
-    if (!have_hist)
-        hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, uint64_t(0),
-                           static_cast<const unsigned long long *>(&counters[C_NEXT]), g->row_ptr, s.acc);
+    hipLaunchKernelGGL(k_frontier_hist, dim3(grid), dim3(256), 0, stream, queue, uint64_t(0),
+                       static_cast<const unsigned long long *>(&counters[C_NEXT]), g->row_ptr, s.acc);
     hipLaunchKernelGGL(k_mlp_pick, dim3(1), dim3(256), 0, stream, s.acc, feature_consts(g, algo, 0),
                        static_cast<const unsigned long long *>(&counters[C_NEXT]), g->mlp_params, g->mlp_range,
                        reinterpret_cast<int *>(&counters[C_CHOICE]), reinterpret_cast<float *>(&counters[C_FEAT]));

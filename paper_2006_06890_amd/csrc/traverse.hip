@@ -1084,13 +1084,10 @@ __global__ __launch_bounds__(kBlock) void k_bits_count(const uint32_t *bits, uin
     }
 }
 
-// hist (optional): the listed vertices' degree histogram for the scheduler
-// (degree_bin counts, then the degree sum), added to *hist.
 __global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t words, const uint32_t *dist,
                                                         uint32_t split, const uint64_t *block_offsets, uint32_t nb,
                                                         uint32_t *queue, uint32_t *also_clear,
-                                                        unsigned long long *ctr, const uint64_t *row_ptr,
-                                                        unsigned long long *hist) {
+                                                        unsigned long long *ctr) {
     const uint64_t base = uint64_t(blockIdx.x) * kBitsTile + uint64_t(threadIdx.x) * kBitsPerThread;
     uint32_t sel[kBitsPerThread];
     uint32_t rest = 0xFFFFFFFFu;  // not used here: k_bits_count reported it
@@ -1119,25 +1116,6 @@ __global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t 
         }
     }
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) ctr[C_NEXT] = block_offsets[blockIdx.x] + tot;
-    if (hist) {
-        __shared__ unsigned long long s_hist[kHistBins + 1];
-        if (threadIdx.x < kHistBins + 1) s_hist[threadIdx.x] = 0;
-        __syncthreads();
-        unsigned long long local[kHistBins + 1] = {};
-#pragma unroll
-        for (int i = 0; i < kBitsPerThread; ++i) {
-            for (uint32_t w = sel[i]; w; w &= w - 1) {
-                const uint64_t v = (base + i) * 32 + uint64_t(__ffs(w) - 1);
-                const uint64_t d = row_ptr[v + 1] - row_ptr[v];
-                local[degree_bin(d)] += 1;
-                local[kHistBins] += d;
-            }
-        }
-        for (int i = 0; i < kHistBins + 1; ++i)
-            if (local[i]) atomicAdd(&s_hist[i], local[i]);
-        __syncthreads();
-        if (threadIdx.x < kHistBins + 1 && s_hist[threadIdx.x]) atomicAdd(&hist[threadIdx.x], s_hist[threadIdx.x]);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1477,8 +1455,7 @@ int choose_variant(emogi_graph_s *g, int algo, uint64_t n, const uint32_t *queue
                    float *features, int *by_network);
 emogi_status_t sched_begin(emogi_graph_s *g, hipStream_t stream);
 emogi_status_t sched_prefetch(emogi_graph_s *g, int algo, const uint32_t *queue, unsigned long long *counters,
-                              hipStream_t stream, bool have_hist);
-unsigned long long *sched_histogram(emogi_graph_s *g);
+                              hipStream_t stream);
 int choose_prefetched(const emogi_graph_s *g, uint64_t n, const unsigned long long *hc, float *features,
                       int *by_network);
 
@@ -1743,17 +1720,13 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
     // Lists the marks in `bits` (with `dist`: those below `cut`) into `queue`
     // in id order, also clearing them in `also_clear`; the count lands in
     // counters[C_NEXT], the smallest distance left marked in C_BANDMIN.
-    // with_hist: also fills the scheduler's degree histogram of the listed
-    // frontier (sched_prefetch then needs no pass of its own).
     auto list_marks = [&](uint32_t *bits, const uint32_t *dist, uint32_t cut, uint32_t *queue,
-                          uint32_t *also_clear, bool with_hist = false) {
-        unsigned long long *hist = with_hist ? sched_histogram(g) : nullptr;
+                          uint32_t *also_clear) {
         hipLaunchKernelGGL(k_bits_count, dim3(nbw), dim3(kBlock), 0, stream, bits, words, dist, cut,
                            p.block_sums, p.counters);
         hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, stream, p.block_sums, nbw);
         hipLaunchKernelGGL(k_bits_write, dim3(nbw), dim3(kBlock), 0, stream, bits, words, dist, cut,
-                           p.block_sums, nbw, queue, also_clear, p.counters,
-                           static_cast<const uint64_t *>(g->row_ptr), hist);
+                           p.block_sums, nbw, queue, also_clear, p.counters);
     };
     auto sync_counters = [&]() -> emogi_status_t {
         EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
@@ -1900,11 +1873,11 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             const uint64_t m = 0x100000000ull - bm;
             split = uint32_t(std::min<uint64_t>(std::max<uint64_t>(m + delta, split), 0xFFFFFFFFull));
             zero_async(p.counters, C_COUNT * sizeof(unsigned long long), stream);
-            list_marks(p.farbits, out, split, p.queue[cur], nullptr, prefetch);
+            list_marks(p.farbits, out, split, p.queue[cur], nullptr);
             if (prefetch) {
                 // the band's first frontier is scored behind its listing and its
                 // pick comes back with the counters
-                emogi_status_t e3 = sched_prefetch(g, algo, p.queue[cur], p.counters, stream, true);
+                emogi_status_t e3 = sched_prefetch(g, algo, p.queue[cur], p.counters, stream);
                 if (e3 != EMOGI_OK) return e3;
             }
             if ((st = sync_counters()) != EMOGI_OK) return st;
@@ -1980,12 +1953,11 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k1, stream), EMOGI_E_HIP);
             if (ordered && !do_bfs) {
-                list_marks(p.nextbits, nullptr, 0xFFFFFFFFu, s.next, algo == A_SSSP ? p.farbits : nullptr,
-                           prefetch);
+                list_marks(p.nextbits, nullptr, 0xFFFFFFFFu, s.next, algo == A_SSSP ? p.farbits : nullptr);
                 EMOGI_HIP_TRY(hipGetLastError(), EMOGI_E_HIP);
             }
             if (prefetch) {
-                emogi_status_t e3 = sched_prefetch(g, algo, s.next, p.counters, stream, ordered && !do_bfs);
+                emogi_status_t e3 = sched_prefetch(g, algo, s.next, p.counters, stream);
                 if (e3 != EMOGI_OK) return e3;
             }
             EMOGI_HIP_TRY(hipMemcpyAsync(p.host_counters, p.counters, C_COUNT * sizeof(unsigned long long),

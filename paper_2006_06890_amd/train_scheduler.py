@@ -42,7 +42,19 @@ def log(*a):
 
 
 PINNED_SCALE = 25  # graphs from this scale on are written straight into pinned memory
-EXCLUDED_LABELS = (0,)  # variants never used as labels (see main)
+
+
+def eligible(X):
+    """The straggler guard of the library's pick (k_mlp_pick) from the
+    features: a thread per vertex (V0) only if every frontier list is below
+    16 ids, a 16-lane group (V1) below 64, a wave (V2, V3) below 4096; the
+    workgroup (V4) and the edge-balanced scan (V5) always.  X[:, 4 + b] > 0:
+    some frontier vertex has a degree in bin b (<=1, [2,4), [4,8), [8,16),
+    [16,64), [64,256), [256,4096), >=4096)."""
+    X = np.asarray(X)
+    has = [(X[:, 4 + b:12] > 0).any(axis=1) for b in range(8)]
+    return np.stack([~has[4], ~has[5], ~has[7], ~has[7],
+                     np.ones(X.shape[0], bool), np.ones(X.shape[0], bool)], axis=1)
 
 
 class _PinnedGraph:
@@ -233,20 +245,19 @@ def main():
             log(f"saved {X.shape[0]} levels to {args.harvest_out}")
         if args.harvest_only:
             return
-    # A thread per vertex (V0) is never a label.  Where it is the fastest it
-    # saves little (87.5 ms over the 8042 levels harvested at R-MAT / uniform
-    # scales 16-27), where it is not it can cost seconds per level (a hub's
-    # list read by one thread: 226 s of regret over the same levels), so a
-    # network that picks it on an unseen graph risks ruinous levels.  The label
-    # is the fastest of the other five variants.
-    allowed = np.array([v for v in range(6) if v not in EXCLUDED_LABELS])
-    y = allowed[np.argmin(T[:, allowed], axis=1)].astype(np.int32)
+    # The label is the fastest variant the library's straggler guard lets the
+    # network pick for that frontier (a worker narrower than the frontier's
+    # longest list is not eligible; see k_mlp_pick): at inference the argmax
+    # is taken over the same variants.
+    ok = eligible(X)
+    Te = np.where(ok, T, np.inf)
+    y = np.argmin(Te, axis=1).astype(np.int32)
     log(f"{X.shape[0]} levels; label histogram {np.bincount(y, minlength=6).tolist()}")
     # Cost-sensitive sampling: a level is repeated in proportion to what a wrong
-    # pick among the allowed variants can cost there (slowest - fastest, in
+    # pick among its eligible variants can cost there (slowest - fastest, in
     # units of 0.05 ms, at most 40 copies), so cheap levels with noisy labels
     # weigh little.
-    spread = T[:, allowed].max(axis=1) - T[:, allowed].min(axis=1)
+    spread = np.where(ok, T, -np.inf).max(axis=1) - Te.min(axis=1)
     copies = 1 + np.minimum(40, np.floor(spread / 0.05)).astype(np.int64)
     Xw, yw = np.repeat(X, copies, axis=0), np.repeat(y, copies)
     # replicate small datasets so every epoch has several full minibatches
@@ -265,7 +276,7 @@ def main():
         "feature_hi": [float(x) for x in hi],
         "train": {"specs": train_specs, "levels": int(X.shape[0]),
                   "label_hist": np.bincount(y, minlength=6).tolist(),
-                  "excluded_labels": list(EXCLUDED_LABELS),
+                  "labels": "fastest eligible variant (straggler guard)",
                   "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                   "epochs": args.epochs},
         "eval": rows,
