@@ -338,8 +338,9 @@ def cpu_baseline(args, rp, col_array, src):
         "threads_used": 1, "host_cpu": host_cpu(),
         "sample": (f"single-threaded oracle queue BFS from source {src} on the benchmark's own graph "
                    f"({workload_name(args)}; {M} directed edges, {reached} reached), read from the same "
-                   f"pinned arrays; {reps} run(s), {secs:.1f}s of CPU.  SSSP and CC not sampled (Dijkstra "
-                   f"and union-find over this graph take minutes on one core)"),
+                   f"pinned arrays; {reps} run(s), {secs:.1f}s of CPU"
+                   + (".  SSSP and CC not sampled (Dijkstra and union-find over this graph take minutes "
+                      "on one core)" if len(args.algos) > 1 else "")),
         "compare_with": "per_algorithm.bfs.gteps" if args.config != "batched26" else "batched.bfs.plain_gteps",
     }
 
@@ -463,9 +464,15 @@ def roofline(args, kernels, peak, profile=None):
         # host-link bytes per launch from TCC_EA0_RDREQ_IO_32B x 32 B (copy-kernel factor applied);
         # FETCH_SIZE (scaled) + WRITE_SIZE per launch beside it for the HBM side
         r["traffic"] = round(ct["link_bytes_per_dispatch"])
-        if r["sector_model_bytes_per_launch"]:
-            r["counted_over_sector_model"] = round(r["traffic"] / r["sector_model_bytes_per_launch"], 4)
-        r["counted_over_algorithmic"] = round(r["traffic"] / max(1, r["algorithmic_bytes_per_launch"]), 4)
+        # the counters come from runs from the first source: compare with that source's models
+        s0 = dom.get("src0", {})
+        if s0.get("launches"):
+            alg0 = s0["bytes"] / s0["launches"]
+            sec0 = s0["sector_bytes"] / s0["launches"]
+            r["first_source"] = {"algorithmic_bytes_per_launch": round(alg0),
+                                 "sector_model_bytes_per_launch": round(sec0),
+                                 "counted_over_algorithmic": round(r["traffic"] / max(1.0, alg0), 4),
+                                 "counted_over_sector_model": round(r["traffic"] / max(1.0, sec0), 4)}
         r["traffic_fetch_write"] = round(ct["fetch_bytes_per_dispatch_scaled"] + ct["write_bytes_per_dispatch"])
         r["traffic_source"] = os.path.relpath(counters_path(args), ROOT)
         if profile and profile.get("hbm_read_GBps"):
@@ -548,13 +555,19 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             else:
                 eb = args.col_bytes + (4 if a == "sssp" else 0)
             sb = (st["id_sector_bytes"] + st["weight_sector_bytes"]) / max(1, st["edges_scanned"])
+            first = s == sources[0]  # the profiled runs traverse from the first source
             for v, ms, ed in zip(st["level_variant"], st["level_ms"], st["level_edges"]):
                 k = kernel_key(a, v, args.col_bytes, args.pack)
-                kk = kernels.setdefault(k, {"ms": 0.0, "bytes": 0, "launches": 0, "sector_bytes": 0})
+                kk = kernels.setdefault(k, {"ms": 0.0, "bytes": 0, "launches": 0, "sector_bytes": 0,
+                                            "src0": {"bytes": 0, "sector_bytes": 0, "launches": 0}})
                 kk["ms"] += ms
                 kk["bytes"] += ed * eb
                 kk["sector_bytes"] += ed * sb
                 kk["launches"] += 1
+                if first:
+                    kk["src0"]["bytes"] += ed * eb
+                    kk["src0"]["sector_bytes"] += ed * sb
+                    kk["src0"]["launches"] += 1
     value = teps_edges / elapsed / 1e9
     link_bytes = sum(p["bytes"] for p in per.values())
     scan_ms = sum(p["scan_ms"] for p in per.values())
@@ -582,7 +595,8 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
     # outputs of the plain zero-copy method for the first source, untimed: every
     # arm below (other placements, tier, packed, batched) must reproduce them
     ref = {}
-    run_step(G, sources[0], out, args.algos, keep=ref)
+    if not (args.no_arms and args.no_batch):
+        run_step(G, sources[0], out, args.algos, keep=ref)
     checks = {}
 
     # --- the two systems patterns, each against the plain method on this GPU ---
@@ -624,6 +638,9 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             r = run_step(G, sources[0], out, args.algos)
             sched[name] = {a: round(r[a]["total_ms"], 2) for a in r}
             sched[name]["step_ms"] = round(sum(r[a]["total_ms"] for a in r), 2)
+            if name == "learned":
+                sched[name]["levels_by_network"] = {a: f"{r[a]['levels_by_network']} of {len(r[a]['level_variant'])}"
+                                                    for a in r}
         result["schedulers"] = sched
         log(f"[bench] schedulers (one step, source {sources[0]}): {sched}")
 
