@@ -1064,17 +1064,39 @@ __device__ __forceinline__ uint32_t band_select(uint32_t w, uint64_t word, const
     return m;
 }
 
+// A thread's kBitsPerThread consecutive words of a mark bitmap: four 16-byte
+// loads when all of them lie inside it (the start is 64-byte aligned), else
+// word by word up to the end.
+__device__ __forceinline__ void load_mark_words(const uint32_t *bits, uint64_t base, uint64_t words,
+                                                uint32_t (&w)[kBitsPerThread]) {
+    static_assert(kBitsPerThread == 16, "four uint4 loads per thread");
+    if (base + kBitsPerThread <= words) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(bits + base);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 x = p[q];
+            w[4 * q] = x.x;
+            w[4 * q + 1] = x.y;
+            w[4 * q + 2] = x.z;
+            w[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kBitsPerThread; ++i) w[i] = base + i < words ? bits[base + i] : 0u;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_bits_count(const uint32_t *bits, uint64_t words, const uint32_t *dist,
                                                         uint32_t split, uint64_t *block_sums,
                                                         unsigned long long *ctr) {
     uint64_t c = 0;
     uint32_t rest = 0xFFFFFFFFu;
     const uint64_t base = uint64_t(blockIdx.x) * kBitsTile + uint64_t(threadIdx.x) * kBitsPerThread;
+    uint32_t wd[kBitsPerThread];
+    load_mark_words(bits, base, words, wd);
+#pragma unroll
     for (int i = 0; i < kBitsPerThread; ++i)
-        if (base + i < words) {
-            const uint32_t w = bits[base + i];
-            if (w) c += __popc(band_select(w, base + i, dist, split, rest));
-        }
+        if (wd[i]) c += __popc(band_select(wd[i], base + i, dist, split, rest));
     uint64_t tot;
     (void)block_exclusive_scan(c, &tot);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
@@ -1092,13 +1114,10 @@ __global__ __launch_bounds__(kBlock) void k_bits_write(uint32_t *bits, uint64_t 
     uint32_t sel[kBitsPerThread];
     uint32_t rest = 0xFFFFFFFFu;  // not used here: k_bits_count reported it
     uint64_t c = 0;
+    load_mark_words(bits, base, words, sel);
 #pragma unroll
     for (int i = 0; i < kBitsPerThread; ++i) {
-        sel[i] = 0;
-        if (base + i < words) {
-            const uint32_t w = bits[base + i];
-            if (w) sel[i] = band_select(w, base + i, dist, split, rest);
-        }
+        if (sel[i]) sel[i] = band_select(sel[i], base + i, dist, split, rest);
         c += __popc(sel[i]);
     }
     uint64_t tot;
