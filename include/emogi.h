@@ -80,8 +80,14 @@ typedef enum {
 /* Scheduler modes for emogi_set_scheduler. */
 #define EMOGI_SCHED_FIXED(v) ((int)(v)) /* always variant v (0..5)                   */
 #define EMOGI_SCHED_HEURISTIC 16        /* rule of thumb on frontier size and degrees */
-#define EMOGI_SCHED_LEARNED 17          /* MLP over frontier features (falls back to the
-                                           heuristic when no weights are loaded)       */
+#define EMOGI_SCHED_LEARNED 17          /* MLP over frontier features: argmax over the
+                                           variants whose worker fits the frontier's
+                                           longest list (a thread below 16 ids, a
+                                           16-lane group below 64, a wave below 4096;
+                                           V4 and V5 always); the heuristic when no
+                                           weights are loaded, a feature lies outside
+                                           the trained range, or the frontier is one
+                                           vertex                                      */
 #define EMOGI_SCHED_PROBE 18            /* time all six variants on every level (state is
                                            saved and restored), then run the fastest: the
                                            per-level best that training labels come from */
