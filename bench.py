@@ -111,7 +111,7 @@ def kernel_key(algo, variant, col_bytes, packed=False):
     t = "unsigned long" if col_bytes == 8 else "unsigned int"
     a = {"bfs": 0, "sssp": 1, "cc": 2}[algo]
     if variant == 6:
-        return f"k_bu_probe<{t}>"
+        return "k_bu_probe_packed" if packed else f"k_bu_probe<{t}>"
     if packed:
         return f"k_balanced_packed<{a}>"
     names = [f"k_group<{t}, {a}, 1>", f"k_group<{t}, {a}, 16>", f"k_wave<{t}, {a}, false>",
@@ -644,7 +644,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         result["schedulers"] = sched
         log(f"[bench] schedulers (one step, source {sources[0]}): {sched}")
 
-    if "bfs" in args.algos and not args.no_arms and not args.pack:
+    if "bfs" in args.algos and not args.no_arms:
         G.set_scheduler("heuristic")
         result["direction"] = {"zero_copy": bfs_directions(G, sources[0], out, ref.get("bfs"))}
         log(f"[bench] direction (zero-copy): {result['direction']['zero_copy']}")
@@ -751,7 +751,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
         create_s = time.perf_counter() - t0
         P.set_scheduler("heuristic")
         ids_b, w_b = P.packed_bytes()
-        ms_a, edges, tot_ms, link = {}, 0, 0.0, {}
+        ms_a, edges, tot_ms, link, bu = {}, 0, 0.0, {}, 0
         for s in sources:
             got = {} if s == sources[0] else None
             r = run_step(P, s, out, args.algos, keep=got)
@@ -759,6 +759,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
                 checks["packed"] = outputs_equal(ref, got)
                 del got
             reached = r["bfs"]["reached_edges"]
+            bu += r["bfs"]["bottom_up_levels"]
             for a in r:
                 ms_a[a] = ms_a.get(a, 0.0) + r[a]["total_ms"]
                 link[a] = link.get(a, 0) + r[a]["useful_link_bytes"]
@@ -771,6 +772,7 @@ def bench_plain(args, E, G, rp, col, w, sources, out, profile, torch, graphgen):
             "gteps": round(edges / (tot_ms * 1e6), 4),
             **{f"{a}_ms": round(ms_a[a] / len(sources), 2) for a in ms_a},
             **{f"{a}_link_GB": round(link[a] / len(sources) / 1e9, 2) for a in link},
+            "bfs_bottom_up_levels_per_run": round(bu / len(sources), 2),
         }
         P.close()
         log(f"[bench] arm packed: {arms['packed']}")

@@ -218,7 +218,8 @@ emogi_status_t emogi_host_free(void *p);
  * weight).  The blocks go where the placement puts the lists;
  * col and weights are read only during creation.  BFS, SSSP, CC and
  * PageRank scan packed lists with the edge-balanced variant (V5) whatever
- * the scheduler; SSSP then reads each scanned list's packed weights whole.
+ * the scheduler (BFS levels may also run bottom-up, see emogi_set_direction);
+ * SSSP then reads each scanned list's packed weights whole.
  * Batched traversal decodes the same blocks.  The HBM tier is
  * EMOGI_E_UNSUPPORTED on packed graphs.
  * Nothing is leaked on failure; *out is set only on success. */
@@ -432,9 +433,10 @@ emogi_status_t emogi_set_hbm_tier(emogi_graph_t g, uint64_t budget_bytes, uint64
  *                        defaults 14 and 24);
  *   EMOGI_DIR_BOTTOM_UP: every level after the source's bottom-up.
  * Bottom-up levels run only on graphs created with EMOGI_F_SYMMETRIC,
- * with the ordered frontier, one level per host wait, plain (not packed)
- * lists and a scheduler mode other than EMOGI_SCHED_PROBE; elsewhere
- * every level is top-down.  stats.level_direction records each level. */
+ * with the ordered frontier, one level per host wait and a scheduler mode
+ * other than EMOGI_SCHED_PROBE; elsewhere every level is top-down.  On
+ * packed lists a bottom-up level decodes a vertex's first 8 ids, then its
+ * blocks in turn.  stats.level_direction records each level. */
 #define EMOGI_DIR_TOP_DOWN 0
 #define EMOGI_DIR_AUTO 1
 #define EMOGI_DIR_BOTTOM_UP 2

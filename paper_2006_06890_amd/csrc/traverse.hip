@@ -479,11 +479,11 @@ struct ChunkGroup {
     uint32_t uv[U];
     uint64_t wbase[U];
     bool tier[U];
-    // packed lists: the word after v[i] (when the gap straddles it), then the
-    // bit shifts and widths of the gap (bits 0-15) and of the weight (16-31),
-    // decoded once the loads are back; SSSP: the weight's words likewise
-    uint32_t hi[U], shw[U];
-    uint32_t wv[U], whi[U];
+    // packed lists: v[i] and wv[i] hold the lane's word of the block's id
+    // and weight parts until the loads are back; pk[i] is the block's gap
+    // width (bits 0-7), weight width (8-15) and id count (16-23)
+    uint32_t pk[U];
+    uint32_t wv[U];
 };
 
 template <class ColT, int A>
@@ -531,10 +531,8 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGro
         g.tier[i] = false;
         g.uv[i] = c.uval;
         if constexpr (kPacked<ColT>) {
-            g.hi[i] = 0;
-            g.shw[i] = 0;
+            g.pk[i] = 0;
             g.wv[i] = 0;
-            g.whi[i] = 0;
         }
         if (kk < c.kend) {
             while (kk >= c.qnext) {  // next entry that owns chunks (uniform)
@@ -557,63 +555,33 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGro
             g.tier[i] = c.src.tier;
             if constexpr (kPacked<ColT>) {
                 // block kk - qfirst of the list (chunks of a packed list are its
-                // blocks: align_mask is 0): lane 0 reads the block's first id,
-                // lane l the gap to id l, bits [(l-1)w, lw) after that word
-                const uint64_t wb = c.pw0 + (kk - c.qfirst) * c.pfull;
-                const uint32_t w = c.pwidth;
-                if (lane == 0) {
-                    // 32-byte sectors of the block's id words (and, for SSSP,
-                    // of the weight words right after them)
-                    const uint64_t cnt = c.e - j0 < uint64_t(kWave) ? c.e - j0 : uint64_t(kWave);
-                    const uint64_t idw = 1 + ((cnt - 1) * w + 31) / 32;
-                    const uint64_t ids = request_bytes(wb, wb + idw, 4, 32) / 32;
-                    t.isect += ids;
-                    if (A == A_SSSP)
-                        t.wsect += request_bytes(wb, wb + idw + (cnt * c.wwidth + 31) / 32, 4, 32) / 32 - ids;
+                // blocks: align_mask is 0): lane l loads word l of the block's
+                // ids and, for SSSP, word l of its weights (which follow the
+                // ids), each word once
+                const uint32_t cnt = uint32_t(c.e - j0 < uint64_t(kWave) ? c.e - j0 : uint64_t(kWave));
+                const uint64_t idb = c.pw0 + (kk - c.qfirst) * c.pfull;
+                const uint32_t idw = packed_id_words(cnt, c.pwidth);
+                if (lane == 0) t.isect += request_bytes(idb, idb + idw, 4, 32) / 32;  // 32-byte sectors
+                if (uint32_t(lane) < idw) g.v[i] = s.pk[idb + lane];
+                if (A == A_SSSP && c.wwidth) {
+                    const uint64_t wtb = idb + idw;
+                    const uint32_t wwd = packed_block_weight_words(cnt, c.wwidth);
+                    if (lane == 0) t.wsect += request_bytes(wtb, wtb + wwd, 4, 32) / 32;
+                    if (uint32_t(lane) < wwd) g.wv[i] = s.pk[wtb + lane];
                 }
-                uint32_t sh = 0;
-                if (g.ok[i]) {
-                    if (lane == 0) {
-                        g.v[i] = s.pk[wb];
-                    } else if (w) {
-                        const uint64_t o = uint64_t(lane - 1) * w;
-                        const uint64_t wd = wb + 1 + (o >> 5);
-                        sh = uint32_t(o & 31u);
-                        g.v[i] = s.pk[wd];
-                        if (sh + w > 32u) g.hi[i] = s.pk[wd + 1];
-                    }
-                }
-                uint32_t wsh = 0, ww = 0;
-                if (A == A_SSSP) {
-                    // the block's weights follow its gap words: lane l's at bits
-                    // [l ww, (l+1) ww) of them
-                    ww = c.wwidth;
-                    if (g.ok[i] && ww) {
-                        const uint64_t cnt = c.e - j0 < uint64_t(kWave) ? c.e - j0 : uint64_t(kWave);
-                        const uint64_t wbase = wb + 1 + ((cnt - 1) * w + 31) / 32;
-                        const uint64_t o = uint64_t(lane) * ww;
-                        const uint64_t wd = wbase + (o >> 5);
-                        wsh = uint32_t(o & 31u);
-                        g.wv[i] = s.pk[wd];
-                        if (wsh + ww > 32u) g.whi[i] = s.pk[wd + 1];
-                    }
-                }
-                g.shw[i] = sh | (w << 8) | (wsh << 16) | (ww << 24);
+                g.pk[i] = c.pwidth | (c.wwidth << 8) | (cnt << 16);
             } else {
                 if (g.ok[i]) g.v[i] = load_col(c.src.col, j - c.src.shift);
             }
         }
     }
     if constexpr (kPacked<ColT>) {
+        // decode from the words the lanes hold (lane moves, no memory access)
 #pragma unroll
         for (int i = 0; i < U; ++i) {
-            const uint32_t sh = g.shw[i] & 0xFFu, w = (g.shw[i] >> 8) & 0xFFu;
-            const uint32_t x = lane != 0 ? packed_field(g.v[i], g.hi[i], sh, w) : g.v[i];
-            g.v[i] = wave_prefix_sum(x, lane);  // first id + the gaps up to each lane
-            if (A == A_SSSP) {
-                const uint32_t wsh = (g.shw[i] >> 16) & 0xFFu, ww = g.shw[i] >> 24;
-                g.wv[i] = packed_field(g.wv[i], g.whi[i], wsh, ww);
-            }
+            const uint32_t w = g.pk[i] & 0xFFu, ww = (g.pk[i] >> 8) & 0xFFu, cnt = g.pk[i] >> 16;
+            g.v[i] = packed_ids(g.v[i], w, cnt, lane);
+            if (A == A_SSSP) g.wv[i] = packed_weights(g.wv[i], ww, lane);
         }
     }
     c.kb += U;
@@ -708,7 +676,11 @@ struct BuArgs {
     uint32_t tag;             // level of the next frontier
     uint32_t *rest;           // vertices left by the probe (k_bu_probe writes, k_bu_rest reads)
     unsigned long long *ctr;  // C_NEXT, C_FEDGES, C_REST, C_EDGES (ids examined), C_IDSECT,
-                              // C_REQBYTES (sectors x 32), C_TIER, C_VERTS (candidates)
+                              // C_REQBYTES (sectors x 32), C_TIER, C_VERTS (candidates),
+                              // C_PKBYTES (packed: encoded bytes read)
+    const uint32_t *pk = nullptr;        // packed lists (EMOGI_F_PACK), or null
+    const uint64_t *pk_off = nullptr;
+    const uint8_t *pk_width = nullptr, *pk_wwidth = nullptr;
 };
 
 __device__ __forceinline__ bool in_frontier(const uint32_t *fbits, uint64_t V, uint32_t x) {
@@ -850,6 +822,167 @@ __global__ __launch_bounds__(kBlock) void k_bu_rest(BuArgs s) {
                     t.isect += sec;
                     t.reqb += 32 * sec;
                 }
+            }
+        }
+        if (hit && lane == 0) {
+            s.level[x] = s.tag;
+            atomicOr(&s.visited[x >> 5], 1u << (x & 31u));
+            atomicOr(&s.nextbits[x >> 5], 1u << (x & 31u));
+            nfound += 1;
+            fedges += e - b;
+        }
+    }
+    flush_tally(t, s.ctr);
+    add_counter(s.ctr, C_NEXT, nfound);
+    add_counter(s.ctr, C_FEDGES, fedges);
+}
+
+// Bottom-up levels over packed lists.  The first 8 ids of a list are its
+// first word and the next 7 gaps, at most 8 words (w <= 32 bits a gap):
+//   k_bu_probe_packed: tiles and candidates as in k_bu_probe; 8 lanes per
+//     candidate load those words (lane j word j, fewer for narrow gaps),
+//     gather each gap from its words' lanes and restore the ids by a prefix
+//     sum inside the 8 lanes; a candidate with no frontier neighbour among
+//     them and more ids is queued for
+//   k_bu_rest_packed: a wave per queued vertex decodes the list's blocks in
+//     turn (block 0 again, its first 8 ids skipped), leaving at the first
+//     frontier neighbour.
+constexpr uint32_t kBuPackedProbeIds = 8;
+
+// Inclusive prefix sum inside each group of 8 lanes (every lane calls it):
+// DPP row shifts by 1, 2 and 4, an added value kept only where it comes
+// from the same group.
+__device__ __forceinline__ uint32_t group8_prefix_sum(uint32_t x, int lane) {
+    constexpr int kRowShr = 0x110;
+    const uint32_t gl = uint32_t(lane) & 7u;
+    uint32_t y = uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 1, 0xf, 0xf, true));
+    x += gl >= 1u ? y : 0u;
+    y = uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 2, 0xf, 0xf, true));
+    x += gl >= 2u ? y : 0u;
+    y = uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 4, 0xf, 0xf, true));
+    x += gl >= 4u ? y : 0u;
+    return x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bu_probe_packed(BuArgs s) {
+    constexpr int G = int(kBuPackedProbeIds);  // lanes per candidate
+    constexpr int S = kWave / G;               // candidates served per step
+    __shared__ uint32_t cand[kWavesPerBlock][kWave];
+    __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
+    __shared__ uint32_t found_w[kWavesPerBlock][2];
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int slot = lane / G, gl = lane % G;
+    const uint64_t gmask = ((uint64_t(1) << G) - 1) << (slot * G);
+    Stage st{seg[wid], 0};
+    Tally t;
+    uint64_t nfound = 0, fedges = 0;
+    const uint64_t words = (s.V + 31) / 32, tiles = (s.V + 63) / 64;
+    for (uint64_t tile = uint64_t(blockIdx.x) * kWavesPerBlock + wid; tile < tiles;
+         tile += uint64_t(gridDim.x) * kWavesPerBlock) {
+        const uint64_t w0 = 2 * tile;
+        const uint32_t vis0 = s.visited[w0], vis1 = w0 + 1 < words ? s.visited[w0 + 1] : ~0u;
+        const uint64_t vis = uint64_t(vis0) | (uint64_t(vis1) << 32);
+        if (vis == ~uint64_t(0)) continue;  // (uniform) nothing left in the tile
+        const uint64_t v = tile * 64 + lane;
+        bool c = v < s.V && !((vis >> lane) & 1u);
+        if (c) c = s.row_ptr[v + 1] > s.row_ptr[v];
+        const uint64_t cm = __ballot(c);
+        if (!cm) continue;
+        if (c) cand[wid][rank_below(cm)] = uint32_t(v);
+        if (lane < 2) found_w[wid][lane] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t nc = uint32_t(__popcll(cm));
+        if (lane == 0) t.verts += nc;
+        for (uint32_t r0 = 0; r0 < nc; r0 += S) {
+            const uint32_t k = r0 + slot;
+            const bool has = k < nc;
+            uint32_t x = 0, w = 0, n = 0, nw = 0;
+            uint64_t b = 0, e = 0, pw0 = 0;
+            if (has) {
+                x = cand[wid][k];
+                b = s.row_ptr[x];
+                e = s.row_ptr[x + 1];
+                pw0 = s.pk_off[x];
+                w = s.pk_width[x];
+                n = e - b < uint64_t(G) ? uint32_t(e - b) : uint32_t(G);  // ids probed (>= 1)
+                nw = packed_id_words(n, w);                                  // their words (<= 8)
+            }
+            const uint32_t word = uint32_t(gl) < nw ? s.pk[pw0 + gl] : 0u;
+            // gap gl of the group's list (lane gl >= 1) from the group's lanes
+            const uint32_t gap = lane_field(word, uint32_t(slot * G + 1), uint32_t(gl) - 1u, w);
+            const bool ok = uint32_t(gl) < n;
+            const uint32_t id = group8_prefix_sum(gl == 0 ? word : (ok ? gap : 0u), lane);
+            const uint64_t fm = __ballot(ok && in_frontier(s.fbits, s.V, id));
+            const bool hit = (fm & gmask) != 0;
+            if (gl == 0 && has) {
+                t.edges += n;
+                const uint64_t sec = request_bytes(pw0, pw0 + nw, 4, 32) / 32;
+                t.isect += sec;
+                t.reqb += 32 * sec;
+                t.pkb += 4 * nw;
+                if (hit) {
+                    s.level[x] = s.tag;
+                    atomicOr(&found_w[wid][(x & 63u) >> 5], 1u << (x & 31u));
+                    fedges += e - b;
+                }
+            }
+            // a candidate with ids left over goes to the wave-per-vertex pass
+            stage(st, gl == 0 && has && !hit && e - b > uint64_t(G), x, s.rest, &s.ctr[C_REST], lane);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t f0 = found_w[wid][0], f1 = found_w[wid][1];
+        if (lane == 0 && (f0 | f1)) {
+            nfound += __popc(f0) + __popc(f1);
+            // the wave owns both words of its tile during this kernel
+            if (f0) {
+                s.visited[w0] = vis0 | f0;
+                s.nextbits[w0] |= f0;
+            }
+            if (f1) {
+                s.visited[w0 + 1] = vis1 | f1;
+                s.nextbits[w0 + 1] |= f1;
+            }
+        }
+    }
+    finish_queue(st, s.rest, &s.ctr[C_REST], lane, wid);
+    flush_tally(t, s.ctr);
+    add_counter(s.ctr, C_NEXT, nfound);
+    add_counter(s.ctr, C_FEDGES, fedges);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bu_rest_packed(BuArgs s) {
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    Tally t;
+    uint64_t nfound = 0, fedges = 0;
+    const uint64_t n = s.ctr[C_REST];
+    const uint64_t nw = uint64_t(gridDim.x) * kWavesPerBlock;
+    for (uint64_t q = uint64_t(blockIdx.x) * kWavesPerBlock + wid; q < n; q += nw) {
+        const uint32_t x = uniform32(s.rest[q]);
+        const uint64_t b = uniform64(s.row_ptr[x]), e = uniform64(s.row_ptr[x + 1]);
+        const uint64_t pw0 = uniform64(s.pk_off[x]);
+        const uint32_t w = uniform32(s.pk_width[x]);
+        const uint32_t full = packed_block_words(w, s.pk_wwidth ? uniform32(s.pk_wwidth[x]) : 0u);
+        bool hit = false;
+        for (uint64_t k = 0; k * kWave < e - b && !hit; ++k) {
+            const uint64_t rest = e - b - k * kWave;
+            const uint32_t cnt = rest < uint64_t(kWave) ? uint32_t(rest) : uint32_t(kWave);
+            const uint64_t idb = pw0 + k * full;
+            const uint32_t id = packed_block(s.pk, idb, w, 0, cnt, lane, nullptr);
+            // block 0's first ids were probed already
+            const bool ok = uint32_t(lane) < cnt && (k > 0 || uint32_t(lane) >= kBuPackedProbeIds);
+            const uint64_t om = __ballot(ok);
+            hit = __ballot(ok && in_frontier(s.fbits, s.V, id)) != 0;
+            if (lane == 0) {
+                const uint32_t idw = packed_id_words(cnt, w);
+                const uint64_t sec = request_bytes(idb, idb + idw, 4, 32) / 32;
+                t.edges += __popcll(om);
+                t.isect += sec;
+                t.reqb += 32 * sec;
+                t.pkb += 4 * idw;
             }
         }
         if (hit && lane == 0) {
@@ -1424,7 +1557,7 @@ static uint32_t level_batch(const emogi_graph_s *g) {
 // direction is picked per level on the host from the ordered frontier.
 static bool direction_allowed(const emogi_graph_s *g) {
     return g->direction != EMOGI_DIR_TOP_DOWN && (g->flags & EMOGI_F_SYMMETRIC) && g->ordered_frontier &&
-           !g->packed.stream && g->sched_mode != EMOGI_SCHED_PROBE && g->V > 0 && level_batch(g) == 1;
+           g->sched_mode != EMOGI_SCHED_PROBE && g->V > 0 && level_batch(g) == 1;
 }
 
 // Direction of the next level (true: bottom-up), from the level just run
@@ -2008,7 +2141,14 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
             const unsigned grid = unsigned(std::max<uint64_t>(
                 1, std::min<uint64_t>((tiles + kWavesPerBlock - 1) / kWavesPerBlock, kMaxGrid)));
             EMOGI_HIP_TRY(hipEventRecord(g->ev_k0, stream), EMOGI_E_HIP);
-            if (colkind) {
+            if (g->packed.stream) {
+                b.pk = g->packed.stream;
+                b.pk_off = g->packed.off;
+                b.pk_width = g->packed.width;
+                b.pk_wwidth = g->packed.wwidth;
+                hipLaunchKernelGGL(k_bu_probe_packed, dim3(grid), dim3(kBlock), 0, stream, b);
+                hipLaunchKernelGGL(k_bu_rest_packed, dim3(kMaxGrid), dim3(kBlock), 0, stream, b);
+            } else if (colkind) {
                 hipLaunchKernelGGL(k_bu_probe<uint64_t>, dim3(grid), dim3(kBlock), 0, stream, b);
                 hipLaunchKernelGGL(k_bu_rest<uint64_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, b);
             } else {

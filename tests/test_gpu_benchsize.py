@@ -52,11 +52,17 @@ def test_packed_rmat20_every_algorithm(gpu_device):
     with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True, pack=True) as G:
         for s in srcs:
             exp = oracle.bfs(g.row_ptr, g.col, s)
+            G.set_direction("top_down")
             G.bfs(s, out)
             np.testing.assert_array_equal(E.to_u32(out), exp, err_msg=f"packed bfs s{s}")
             st = G.stats()
             assert set(st["level_variant"]) == {5}
             assert max(st["level_edges"]) > PASS_IDS, "no BFS level wraps the packed grid"
+            # the direction rule: bottom-up middle levels over the packed lists
+            G.set_direction("auto")
+            G.bfs(s, out)
+            np.testing.assert_array_equal(E.to_u32(out), exp, err_msg=f"packed bfs auto s{s}")
+            assert G.stats()["bottom_up_levels"] >= 1
             G.sssp(s, out)
             np.testing.assert_array_equal(E.to_u32(out), oracle.dijkstra(g.row_ptr, g.col, g.weights, s),
                                           err_msg=f"packed sssp s{s}")

@@ -5,7 +5,7 @@
   heuristic scheduler, 256-byte request unit; BFS with its default
   per-level direction and all top-down; then the same pinned arrays as
   packed lists (gaps of up to 27 bits, every packed launch wrapping its
-  grid).  BFS levels and CC labels are
+  grid), BFS again both ways.  BFS levels and CC labels are
   compared with the oracle element by element; SSSP distances (Dijkstra on 4
   billion edges is too slow for a test) are checked with the oracle's exact
   linear-time certificate, which holds iff the vector equals the true
@@ -69,19 +69,26 @@ def test_fullsize_kron27_u64_zero_copy(gpu_device):
     with E.Graph(rp, col, w, symmetric=True, borrow=True, pack=True) as P:
         P.bfs(src, out)
         p_lv = E.to_u32(out)
+        p_bu = P.stats()["bottom_up_levels"]
+        P.set_direction("top_down")
+        P.bfs(src, out)
+        p_lv_td = E.to_u32(out)
         p_edges = max(P.stats()["level_edges"])
+        P.set_direction("auto")
         P.sssp(src, out)
         p_dist = E.to_u32(out)
         P.cc(out)
         p_lab = E.to_u32(out)
     assert p_edges > 65536 * 64, "no packed BFS level wraps the edge-balanced grid"
-    say("packed traversals done; running the oracle")
+    assert p_bu >= 1, "no bottom-up level on the packed lists"
+    say(f"packed traversals done ({p_bu} bottom-up BFS levels); running the oracle")
     t = time.time()
     ref = oracle.bfs(rp, col.array, src)
     assert np.array_equal(lv, ref), "BFS levels differ from the oracle"
     assert np.array_equal(lv_td, ref), "top-down BFS levels differ from the oracle"
     assert np.array_equal(p_lv, ref), "packed BFS levels differ from the oracle"
-    say(f"BFS equal: direction-optimizing, top-down, packed ({time.time() - t:.0f}s)")
+    assert np.array_equal(p_lv_td, ref), "packed top-down BFS levels differ from the oracle"
+    say(f"BFS equal: direction-optimizing, top-down, packed both ways ({time.time() - t:.0f}s)")
     t = time.time()
     assert oracle.certify_distances(rp, col.array, src, dist, w.array) == 0, "SSSP certificate failed"
     assert np.array_equal(p_dist, dist), "packed SSSP distances differ"

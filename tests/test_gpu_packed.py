@@ -128,6 +128,7 @@ def test_packed_link_bytes(gpu_device):
     words = _packed_words(g.row_ptr, g.col)
     out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
     with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True, pack=True) as G:
+        G.set_direction("top_down")
         s = int(np.argmax(g.degrees()))
         G.bfs(s, out)
         lv = E.to_u32(out)
@@ -149,6 +150,67 @@ def test_packed_link_bytes(gpu_device):
             G.bfs(s, out)
             np.testing.assert_array_equal(E.to_u32(out), lv)
             assert set(G.stats()["level_variant"]) == {5}, mode
+
+
+def _long_list_graph():
+    """Lists whose first ids hold no frontier vertex: a star's hub reached
+    from a leaf, a clique and a star in other components (their vertices
+    read their whole lists and stay unreached), and a hub of 601 ids whose
+    only frontier neighbour is its last id."""
+    n = 3000
+    edges = [(0, i) for i in range(1, n)]
+    edges += [(n + a, n + b) for a in range(70) for b in range(a + 1, 70)]
+    edges += [(n + 100, n + 101 + i) for i in range(500)]
+    edges += [(n + 700 + i, n + 1300) for i in range(600)]
+    edges += [(n + 1300, n + 1301), (n + 1301, n + 1302)]
+    return graphgen.from_edges(n + 1400, np.array(edges), symmetric=True), [1, 0, n + 5, n + 1302, n + 700, n + 1399]
+
+
+def test_packed_bottom_up_levels(gpu_device):
+    """Bottom-up BFS levels on packed lists (the first 8 ids of every
+    unvisited vertex decoded in 8 lanes, then its blocks in turn) give the
+    oracle's levels: every level after the source's forced bottom-up, the
+    direction rule with its defaults and with alpha 1 (bottom-up as soon as
+    the frontier grows), on both id widths and both placements."""
+    import torch
+    import paper_2006_06890_amd as E
+    from test_gpu_direction import _check_bfs
+    cases = [(name, GRAPHS[name], _sources(GRAPHS[name])) for name in sorted(GRAPHS) if SYMMETRIC[name]]
+    cases.append(("long lists",) + _long_list_graph())
+    for name, g, sources in cases:
+        for col_bytes, placement in ((4, "host_zero_copy"), (8, "hbm")):
+            col = g.col.astype(np.uint32 if col_bytes == 4 else np.uint64)
+            out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+            print(f"[packed bottom-up] {name} V={g.num_vertices} e={col_bytes} {placement}", flush=True)
+            with E.Graph(g.row_ptr, col, g.weights, placement=placement, symmetric=True, pack=True) as G:
+                for mode, alpha, beta in (("bottom_up", 0, 0), ("auto", 14, 24), ("auto", 1, 1000000)):
+                    G.set_direction(mode, alpha, beta)
+                    for s in sources:
+                        st = _check_bfs(E, G, g, s, out, mode, f"packed {name} {mode} a{alpha}")
+                        if mode == "bottom_up" and st["iterations"] > 1:
+                            assert st["bottom_up_levels"] == st["iterations"] - 1
+
+
+def test_packed_bottom_up_reads_less(gpu_device):
+    """On R-MAT the direction rule takes the big middle levels bottom-up and
+    the packed BFS then reads far fewer encoded bytes than the top-down one,
+    which reads every reached list once."""
+    import torch
+    import paper_2006_06890_amd as E
+    g = GRAPHS["rmat13"]
+    out = torch.empty(g.num_vertices, dtype=torch.int32, device="cuda")
+    s = int(np.argmax(g.degrees()))
+    exp = oracle.bfs(g.row_ptr, g.col, s)
+    with E.Graph(g.row_ptr, g.col, g.weights, symmetric=True, pack=True) as G:
+        got = {}
+        for mode in ("top_down", "auto"):
+            G.set_direction(mode)
+            G.bfs(s, out)
+            np.testing.assert_array_equal(E.to_u32(out), exp, err_msg=mode)
+            got[mode] = G.stats()
+        assert got["auto"]["bottom_up_levels"] >= 1, got["auto"]["level_direction"]
+        assert got["auto"]["useful_link_bytes"] < 0.6 * got["top_down"]["useful_link_bytes"]
+        assert got["auto"]["edges_scanned"] < got["top_down"]["edges_scanned"]
 
 
 @pytest.mark.parametrize("id_bits", [25, 28])
