@@ -566,7 +566,9 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGro
                 if (A == A_SSSP && c.wwidth) {
                     const uint64_t wtb = idb + idw;
                     const uint32_t wwd = packed_block_weight_words(cnt, c.wwidth);
-                    if (lane == 0) t.wsect += request_bytes(wtb, wtb + wwd, 4, 32) / 32;
+                    // the sectors the weight words add to the id words' ones
+                    if (lane == 0)
+                        t.wsect += request_bytes(idb, wtb + wwd, 4, 32) / 32 - request_bytes(idb, wtb, 4, 32) / 32;
                     if (uint32_t(lane) < wwd) g.wv[i] = s.pk[wtb + lane];
                 }
                 g.pk[i] = c.pwidth | (c.wwidth << 8) | (cnt << 16);
@@ -663,6 +665,8 @@ __global__ __launch_bounds__(kBlock) void k_balanced_packed(ScanArgs s0, OpArgs 
 //     stopped, leaving at the first frontier neighbour.
 // ---------------------------------------------------------------------------
 constexpr int kBuProbeSectors = 2;
+// Ids of a packed list the bottom-up probe decodes per unvisited vertex.
+constexpr int kBuPackedProbeIds = 8;
 
 struct BuArgs {
     const uint64_t *row_ptr;
@@ -837,36 +841,40 @@ __global__ __launch_bounds__(kBlock) void k_bu_rest(BuArgs s) {
     add_counter(s.ctr, C_FEDGES, fedges);
 }
 
-// Bottom-up levels over packed lists.  The first 8 ids of a list are its
-// first word and the next 7 gaps, at most 8 words (w <= 32 bits a gap):
-//   k_bu_probe_packed: tiles and candidates as in k_bu_probe; 8 lanes per
+// Bottom-up levels over packed lists.  The first G ids of a list are its
+// first word and the next G - 1 gaps, at most G words (w <= 32 bits a gap):
+//   k_bu_probe_packed<G>: tiles and candidates as in k_bu_probe; G lanes per
 //     candidate load those words (lane j word j, fewer for narrow gaps),
 //     gather each gap from its words' lanes and restore the ids by a prefix
-//     sum inside the 8 lanes; a candidate with no frontier neighbour among
+//     sum inside the G lanes; a candidate with no frontier neighbour among
 //     them and more ids is queued for
-//   k_bu_rest_packed: a wave per queued vertex decodes the list's blocks in
-//     turn (block 0 again, its first 8 ids skipped), leaving at the first
+//   k_bu_rest_packed<G>: a wave per queued vertex decodes the list's blocks
+//     in turn (block 0 again, its first G ids skipped), leaving at the first
 //     frontier neighbour.
-constexpr uint32_t kBuPackedProbeIds = 8;
-
-// Inclusive prefix sum inside each group of 8 lanes (every lane calls it):
-// DPP row shifts by 1, 2 and 4, an added value kept only where it comes
-// from the same group.
-__device__ __forceinline__ uint32_t group8_prefix_sum(uint32_t x, int lane) {
+// Inclusive prefix sum inside each group of G (8 or 16) lanes (every lane
+// calls it): DPP row shifts by 1, 2, 4 (and 8), an added value kept only
+// where it comes from the same group.
+template <int G>
+__device__ __forceinline__ uint32_t group_prefix_sum(uint32_t x, int lane) {
+    static_assert(G == 8 || G == 16, "groups of 8 or 16 lanes");
     constexpr int kRowShr = 0x110;
-    const uint32_t gl = uint32_t(lane) & 7u;
+    const uint32_t gl = uint32_t(lane) & uint32_t(G - 1);
     uint32_t y = uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 1, 0xf, 0xf, true));
     x += gl >= 1u ? y : 0u;
     y = uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 2, 0xf, 0xf, true));
     x += gl >= 2u ? y : 0u;
     y = uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 4, 0xf, 0xf, true));
     x += gl >= 4u ? y : 0u;
+    if constexpr (G == 16) {
+        y = uint32_t(__builtin_amdgcn_update_dpp(0, int(x), kRowShr + 8, 0xf, 0xf, true));
+        x += gl >= 8u ? y : 0u;
+    }
     return x;
 }
 
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_bu_probe_packed(BuArgs s) {
-    constexpr int G = int(kBuPackedProbeIds);  // lanes per candidate
-    constexpr int S = kWave / G;               // candidates served per step
+    constexpr int S = kWave / G;  // candidates served per step
     __shared__ uint32_t cand[kWavesPerBlock][kWave];
     __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
     __shared__ uint32_t found_w[kWavesPerBlock][2];
@@ -907,13 +915,13 @@ __global__ __launch_bounds__(kBlock) void k_bu_probe_packed(BuArgs s) {
                 pw0 = s.pk_off[x];
                 w = s.pk_width[x];
                 n = e - b < uint64_t(G) ? uint32_t(e - b) : uint32_t(G);  // ids probed (>= 1)
-                nw = packed_id_words(n, w);                                  // their words (<= 8)
+                nw = packed_id_words(n, w);                                  // their words (<= G)
             }
             const uint32_t word = uint32_t(gl) < nw ? s.pk[pw0 + gl] : 0u;
             // gap gl of the group's list (lane gl >= 1) from the group's lanes
             const uint32_t gap = lane_field(word, uint32_t(slot * G + 1), uint32_t(gl) - 1u, w);
             const bool ok = uint32_t(gl) < n;
-            const uint32_t id = group8_prefix_sum(gl == 0 ? word : (ok ? gap : 0u), lane);
+            const uint32_t id = group_prefix_sum<G>(gl == 0 ? word : (ok ? gap : 0u), lane);
             const uint64_t fm = __ballot(ok && in_frontier(s.fbits, s.V, id));
             const bool hit = (fm & gmask) != 0;
             if (gl == 0 && has) {
@@ -954,6 +962,7 @@ __global__ __launch_bounds__(kBlock) void k_bu_probe_packed(BuArgs s) {
     add_counter(s.ctr, C_FEDGES, fedges);
 }
 
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_bu_rest_packed(BuArgs s) {
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     Tally t;
@@ -973,7 +982,7 @@ __global__ __launch_bounds__(kBlock) void k_bu_rest_packed(BuArgs s) {
             const uint64_t idb = pw0 + k * full;
             const uint32_t id = packed_block(s.pk, idb, w, 0, cnt, lane, nullptr);
             // block 0's first ids were probed already
-            const bool ok = uint32_t(lane) < cnt && (k > 0 || uint32_t(lane) >= kBuPackedProbeIds);
+            const bool ok = uint32_t(lane) < cnt && (k > 0 || lane >= G);
             const uint64_t om = __ballot(ok);
             hit = __ballot(ok && in_frontier(s.fbits, s.V, id)) != 0;
             if (lane == 0) {
@@ -2146,8 +2155,8 @@ static emogi_status_t traverse(emogi_graph_s *g, int algo, uint64_t src, uint32_
                 b.pk_off = g->packed.off;
                 b.pk_width = g->packed.width;
                 b.pk_wwidth = g->packed.wwidth;
-                hipLaunchKernelGGL(k_bu_probe_packed, dim3(grid), dim3(kBlock), 0, stream, b);
-                hipLaunchKernelGGL(k_bu_rest_packed, dim3(kMaxGrid), dim3(kBlock), 0, stream, b);
+                hipLaunchKernelGGL(k_bu_probe_packed<kBuPackedProbeIds>, dim3(grid), dim3(kBlock), 0, stream, b);
+                hipLaunchKernelGGL(k_bu_rest_packed<kBuPackedProbeIds>, dim3(kMaxGrid), dim3(kBlock), 0, stream, b);
             } else if (colkind) {
                 hipLaunchKernelGGL(k_bu_probe<uint64_t>, dim3(grid), dim3(kBlock), 0, stream, b);
                 hipLaunchKernelGGL(k_bu_rest<uint64_t>, dim3(kMaxGrid), dim3(kBlock), 0, stream, b);

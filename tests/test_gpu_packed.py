@@ -71,6 +71,26 @@ def _packed_weight_words(rp, w):
     return words
 
 
+def _id_sectors(rp, col, w):
+    """Per list, the 32-byte sectors of its blocks' id words when every
+    block is read on its own: the lists lie one after another, and in each
+    block the id words are followed by the block's weight words."""
+    V = rp.shape[0] - 1
+    sectors = np.zeros(V, dtype=np.int64)
+    off = 0
+    for u in range(V):
+        ids = [int(x) for x in col[int(rp[u]):int(rp[u + 1])]]
+        ws = [int(x) for x in w[int(rp[u]):int(rp[u + 1])]]
+        blocks = [ids[k:k + 64] for k in range(0, len(ids), 64)]
+        gw = max((b[i + 1] - b[i] for b in blocks for i in range(len(b) - 1)), default=0).bit_length()
+        ww = max(ws, default=0).bit_length()
+        for b in blocks:
+            idw = 1 + ((len(b) - 1) * gw + 31) // 32
+            sectors[u] += ((off + idw) * 4 + 31) // 32 - (off * 4) // 32
+            off += idw + (len(b) * ww + 31) // 32
+    return sectors
+
+
 def _sources(g):
     deg = g.degrees()
     nz = np.flatnonzero(deg > 0)
@@ -137,6 +157,7 @@ def test_packed_link_bytes(gpu_device):
         assert st["edges_scanned"] == int(g.degrees()[reached].sum())
         assert st["useful_link_bytes"] == 4 * int(words[reached].sum())
         assert st["request_bytes"] >= st["useful_link_bytes"]
+        assert st["id_sector_bytes"] == 32 * int(_id_sectors(g.row_ptr, g.col, g.weights)[reached].sum())
         assert G.packed_bytes()[0] < 0.6 * 4 * g.num_edges      # ids: well under 4 bytes
         # weights 1..255: at most 8 bits each, each list rounded up to a word
         assert G.packed_bytes()[1] <= g.num_edges + 3 * int((g.degrees() > 0).sum())
