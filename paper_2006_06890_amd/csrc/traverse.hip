@@ -1322,34 +1322,34 @@ __global__ __launch_bounds__(kBlock) void k_cc_sample(const uint64_t *row_ptr, c
     flush_tally(t, ctr);
 }
 
-// Sampled hooking on packed lists: the first ids of block 0 of each list.
+// Sampled hooking on packed lists: the first two ids of block 0 of each
+// list, its first word and the gap at the start of the next word.  Both
+// words are loaded before the first hook, so the two host reads of a thread
+// overlap instead of waiting on the hook's HBM atomics.
 __global__ __launch_bounds__(kBlock) void k_cc_sample_packed(const uint64_t *row_ptr, const uint32_t *pk,
                                                              const uint64_t *pk_off, const uint8_t *pk_width,
                                                              uint64_t V, uint32_t *parent,
                                                              unsigned long long *ctr) {
+    static_assert(kCcSample == 2, "the sample is a list's first word and the gap after it");
     uint64_t edges = 0, pkb = 0, isect = 0;
     for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < V;
          v += uint64_t(gridDim.x) * blockDim.x) {
         const uint64_t d = row_ptr[v + 1] - row_ptr[v];
-        const uint32_t n = d < kCcSample ? uint32_t(d) : uint32_t(kCcSample);
-        if (n == 0) continue;
+        if (d == 0) continue;
         const uint64_t w0 = pk_off[v];
         const uint32_t w = pk_width[v];
-        uint32_t x = pk[w0];
-        if (x < V) uf_link(parent, uint32_t(v), x);
-        const uint64_t words = 1 + (n > 1 && w ? (uint64_t(n - 1) * w + 31) / 32 : 0);
+        const bool second = d > 1;
+        const uint32_t words = second && w ? 2u : 1u;  // a zero gap width stores no gap words
+        const uint32_t x0 = pk[w0];
+        const uint32_t g1 = words == 2u ? pk[w0 + 1] : 0u;
         pkb += 4 * words;
         isect += request_bytes(w0, w0 + words, 4, 32) / 32;
-        for (uint32_t r = 1; r < n; ++r) {
-            const uint64_t o = uint64_t(r - 1) * w;
-            const uint64_t wd = w0 + 1 + (o >> 5);
-            const uint32_t sh = uint32_t(o & 31u);
-            uint64_t word = w ? pk[wd] : 0u;
-            if (w && sh + w > 32u) word |= uint64_t(pk[wd + 1]) << 32;
-            x += uint32_t((word >> sh) & ((uint64_t(1) << w) - 1));
-            if (x < V) uf_link(parent, uint32_t(v), x);
+        if (x0 < V) uf_link(parent, uint32_t(v), x0);
+        if (second) {
+            const uint32_t x1 = x0 + packed_field(g1, 0u, 0u, w);
+            if (x1 < V) uf_link(parent, uint32_t(v), x1);
         }
-        edges += n;
+        edges += second ? 2 : 1;
     }
     add_counter(ctr, C_EDGES, edges);
     add_counter(ctr, C_PKBYTES, pkb);
