@@ -110,8 +110,8 @@ def kernel_key(algo, variant, col_bytes, packed=False):
     a bottom-up BFS level, whose probe kernel carries nearly all its time)."""
     t = "unsigned long" if col_bytes == 8 else "unsigned int"
     a = {"bfs": 0, "sssp": 1, "cc": 2}[algo]
-    if variant == 6:
-        return "k_bu_probe_packed" if packed else f"k_bu_probe<{t}>"
+    if variant == 6:  # packed: the probe decodes 8 ids per vertex
+        return "k_bu_probe_packed<8>" if packed else f"k_bu_probe<{t}>"
     if packed:
         return f"k_balanced_packed<{a}>"
     names = [f"k_group<{t}, {a}, 1>", f"k_group<{t}, {a}, 16>", f"k_wave<{t}, {a}, false>",

@@ -27,6 +27,8 @@ def test_profiler_names_shorten_to_kernel_keys():
     assert bench._short_name("emogi::k_bits_count(unsigned int const*, unsigned long)") == "k_bits_count"
     assert bench._short_name("void emogi::k_balanced_packed<0>(emogi::ScanArgs, emogi::OpArgs)") == \
         bench.kernel_key("bfs", 5, 8, packed=True)
+    assert bench._short_name("void emogi::k_bu_probe_packed<8>(emogi::BuArgs)") == \
+        bench.kernel_key("bfs", 6, 8, packed=True)
 
 
 def test_counter_files_and_workload_names():
