@@ -480,9 +480,9 @@ struct ChunkGroup {
     uint64_t wbase[U];
     bool tier[U];
     // packed lists: v[i] and wv[i] hold the lane's word of the block's id
-    // and weight parts until the loads are back; pk[i] is the block's gap
+    // and weight parts until the loads are back; shape[i] is the block's gap
     // width (bits 0-7), weight width (8-15) and id count (16-23)
-    uint32_t pk[U];
+    uint32_t shape[U];
     uint32_t wv[U];
 };
 
@@ -531,7 +531,7 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGro
         g.tier[i] = false;
         g.uv[i] = c.uval;
         if constexpr (kPacked<ColT>) {
-            g.pk[i] = 0;
+            g.shape[i] = 0;
             g.wv[i] = 0;
         }
         if (kk < c.kend) {
@@ -571,7 +571,7 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGro
                         t.wsect += request_bytes(idb, wtb + wwd, 4, 32) / 32 - request_bytes(idb, wtb, 4, 32) / 32;
                     if (uint32_t(lane) < wwd) g.wv[i] = s.pk[wtb + lane];
                 }
-                g.pk[i] = c.pwidth | (c.wwidth << 8) | (cnt << 16);
+                g.shape[i] = c.pwidth | (c.wwidth << 8) | (cnt << 16);
             } else {
                 if (g.ok[i]) g.v[i] = load_col(c.src.col, j - c.src.shift);
             }
@@ -581,7 +581,7 @@ __device__ __forceinline__ void load_group(ChunkCursor<ColT> &c, ChunkGroup<kGro
         // decode from the words the lanes hold (lane moves, no memory access)
 #pragma unroll
         for (int i = 0; i < U; ++i) {
-            const uint32_t w = g.pk[i] & 0xFFu, ww = (g.pk[i] >> 8) & 0xFFu, cnt = g.pk[i] >> 16;
+            const uint32_t w = g.shape[i] & 0xFFu, ww = (g.shape[i] >> 8) & 0xFFu, cnt = g.shape[i] >> 16;
             g.v[i] = packed_ids(g.v[i], w, cnt, lane);
             if (A == A_SSSP) g.wv[i] = packed_weights(g.wv[i], ww, lane);
         }
@@ -637,8 +637,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     balanced_body<ColT, A>(s0, a, seg);
 }
 
-// V5 over packed lists; the decoding needs more registers than the 6 waves
-// per SIMD of the plain kernel allow without spilling.
+// V5 over packed lists, a kernel of its own: the decoding sets its register
+// use (SSSP 120 VGPRs, 4 waves per SIMD; BFS 86, 5 waves), uncapped.
 template <int A>
 __global__ __launch_bounds__(kBlock) void k_balanced_packed(ScanArgs s0, OpArgs a) {
     __shared__ uint32_t seg[kWavesPerBlock][kSegCap];
@@ -851,6 +851,7 @@ __global__ __launch_bounds__(kBlock) void k_bu_rest(BuArgs s) {
 //   k_bu_rest_packed<G>: a wave per queued vertex decodes the list's blocks
 //     in turn (block 0 again, its first G ids skipped), leaving at the first
 //     frontier neighbour.
+
 // Inclusive prefix sum inside each group of G (8 or 16) lanes (every lane
 // calls it): DPP row shifts by 1, 2, 4 (and 8), an added value kept only
 // where it comes from the same group.
